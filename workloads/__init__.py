@@ -1,0 +1,123 @@
+"""Seeded synthetic workloads for the low-rank isogeometric Poisson solver.
+
+This module only draws random numbers and writes down recipes (which 1D
+matrices make up each Kronecker term, which weights they carry, which seeds
+feed the right-hand side).  It performs none of the method's arithmetic:
+no B-spline evaluation, no quadrature, no tensor algebra.  Both the CPU
+oracle and the GPU library build their matrices and vectors from these
+recipes independently.
+
+Recipe vocabulary
+-----------------
+A 1D matrix is ``(kind, weight)`` with ``kind`` in ``{"mass", "stiff",
+"mixed10", "mixed01"}`` (``mixed10`` differentiates the test function,
+``mixed01`` the trial function) and ``weight = (c0, c1, a, b)`` meaning
+``w(x) = c0 + c1*cos(a*x + b)`` on the parametric interval [0, 1].
+
+An operator is the Tucker matrix of eq. (tucker_matrix): per mode ``k`` a
+list of distinct 1D matrices, plus the nonzeros ``(i1, i2, i3, c)`` of its
+core.  A sum of R Kronecker terms is the superdiagonal-core special case.
+
+A right-hand side is a Tucker vector: either ``{"kind": "random", "core",
+"factors"}`` (values given) or ``{"kind": "load", "weight"}`` meaning the 1D
+moments F_i = int b_i(x) w(x) dx in every mode with core [[[1]]] (the
+separable load of Appendix A with a single term).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+UNIT = (1.0, 0.0, 0.0, 0.0)          # w(x) = 1
+SIN_PI = (0.0, 1.0, math.pi, -0.5 * math.pi)   # w(x) = cos(pi x - pi/2) = sin(pi x)
+
+
+@dataclass
+class Workload:
+    name: str
+    n_el: int
+    p: int
+    modes: list            # modes[k] = list of (kind, weight)
+    nnz: list              # list of (i1, i2, i3, coef)
+    rhs: dict
+    tol: float = 1e-6
+    eps_min: float | None = None      # None: 0.1 * tol (paper, Sec. 5)
+    params: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        """Interior dofs per direction, n = n_el + p - 2 (Dirichlet space)."""
+        return self.n_el + self.p - 2
+
+
+def laplace_cube(n_el: int, p: int, name: str | None = None) -> Workload:
+    """-Laplace on the unit cube: K(x)M(x)M + M(x)K(x)M + M(x)M(x)K with the
+    unweighted 1D stiffness K and mass M; rhs = moments of prod sin(pi x_i)."""
+    modes = [[("stiff", UNIT), ("mass", UNIT)] for _ in range(3)]
+    nnz = [(0, 1, 1, 1.0), (1, 0, 1, 1.0), (1, 1, 0, 1.0)]
+    return Workload(name or f"laplace_cube_nel{n_el}_p{p}", n_el, p, modes, nnz,
+                    {"kind": "load", "weight": SIN_PI})
+
+
+def weighted_cp(n_el: int, p: int, R: int, rank: int, seed_op: int,
+                seed_rhs: int, name: str | None = None,
+                amp: float = 0.5) -> Workload:
+    """Deformed-geometry stand-in: R Kronecker terms; term t has the stiffness
+    matrix in direction t mod 3 and mass matrices in the other two; every 1D
+    factor (k, t) carries its own weight 1 + amp*cos(a x + b) with a, b drawn
+    i.i.d. from U[0, 2].  rhs: Tucker rank `rank`, core and factors N(0, 1)."""
+    rng = np.random.default_rng(seed_op)
+    ab = rng.uniform(0.0, 2.0, size=(R, 3, 2))
+    modes = [[] for _ in range(3)]
+    for t in range(R):
+        for k in range(3):
+            kind = "stiff" if k == t % 3 else "mass"
+            a, b = float(ab[t, k, 0]), float(ab[t, k, 1])
+            modes[k].append((kind, (1.0, amp, a, b)))
+    nnz = [(t, t, t, 1.0) for t in range(R)]
+    return Workload(name or f"weighted_cp_nel{n_el}_p{p}_R{R}_r{rank}", n_el, p,
+                    modes, nnz, random_rhs(n_el + p - 2, rank, seed_rhs))
+
+
+def random_rhs(n: int, rank: int, seed: int, ranks=None) -> dict:
+    rng = np.random.default_rng(seed)
+    r = tuple(ranks) if ranks is not None else (rank, rank, rank)
+    core = rng.standard_normal(r)
+    factors = [rng.standard_normal((n, r[k])) for k in range(3)]
+    return {"kind": "random", "core": core, "factors": factors}
+
+
+def random_tucker(n, ranks, seed):
+    """A random Tucker tensor (core, [U1, U2, U3]) with N(0,1) entries; `n`
+    may be an int or a 3-tuple."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    rng = np.random.default_rng(seed)
+    core = rng.standard_normal(tuple(ranks))
+    factors = [rng.standard_normal((nn[k], ranks[k])) for k in range(3)]
+    return core, factors
+
+
+# --- the benchmark configurations -------------------------------------------
+
+def config_small() -> Workload:
+    """3D Poisson on the unit cube, p = 2, n_el = 16 (16 dofs/direction),
+    rhs = projected prod sin(pi x_i); tol 1e-6, truncation floor 1e-8."""
+    w = laplace_cube(16, 2, name="poisson_cube_p2_nel16")
+    w.eps_min = 1e-8
+    return w
+
+
+def config_deformed() -> Workload:
+    """Deformed-geometry Poisson stand-in: p = 3, n_el = 128 (129 dofs),
+    9 weighted Kronecker terms (seed 2002), rhs Tucker rank 5 (seed 2003)."""
+    return weighted_cp(128, 3, 9, 5, 2002, 2003,
+                       name="poisson_weighted9_p3_nel128_r5")
+
+
+def config_large() -> Workload:
+    """Large single solve: p = 3, n_el = 512 (515 dofs), 12 weighted terms
+    (seed 3002), rhs Tucker rank 10 (seed 3003)."""
+    return weighted_cp(512, 3, 12, 10, 3002, 3003,
+                       name="poisson_weighted12_p3_nel512_r10")
