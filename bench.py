@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Benchmark: TPCG solves/s on one MI355X.
+
+One step = one complete TPCG solve (Algorithm 5) of the deformed-geometry
+Poisson workload: p = 3, n_el = 128 (129 dofs per direction), 9 weighted
+Kronecker terms, rhs of Tucker rank 5, tol 1e-6, FP64.  Every step runs the
+whole hot path (operator application, low-rank FD preconditioner, relative
+and dynamic truncation, Tucker dots).  Inputs (operator bands, FD setup,
+rhs) are resident in HBM before the timed region.
+
+Prints one JSON line (see the "metric" key) with:
+  value/ms_per_step    solves/s and mean solve time over the timed steps
+  latency_ms           p50/p99 of the per-solve times
+  kernels              per-family launches, time, algorithmic GB/s and GFLOP/s
+                       measured with HIP events on the library's stream
+  roofline             the dominant kernel family against its MI355X peak
+  cpu_baseline         the FP64 oracle on the host cores (bounded sample)
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload deformed|small]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TPCG solves/sec + p50/p99 latency at rel. err 1e-6; HBM GB/s of mode products"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+
+def workload(name):
+    import workloads as W
+    return {"deformed": W.config_deformed, "small": W.config_small, "large": W.config_large}[name]()
+
+
+def cpu_baseline(w, gpu_iters, budget_s=30.0):
+    """The oracle's TPCG (unchanged) on a bounded sample: the first TPCG
+    iteration of the same solve (including the initial preconditioner and
+    operator truncations), extrapolated to a whole solve by the GPU run's
+    iteration count."""
+    import numpy as np
+    from oracle import fd as ofd, problem as oprob, tpcg as otpcg
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    op = oprob.operator(w)
+    f = oprob.rhs(w)
+    prec = ofd.LowRankFD(w.n_el, w.p, 0.1)
+    t0 = time.perf_counter()
+    x, info = otpcg.tpcg(op, prec, f, tol=w.tol, eps_min=w.eps_min, maxit=1)
+    dt = time.perf_counter() - t0
+    per_solve = dt * max(gpu_iters, 1)
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"first TPCG iteration of the same solve ({dt:.1f} s, numpy/scipy FP64), "
+                      f"scaled by the GPU solve's {gpu_iters} iterations",
+            "sample_seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="deformed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); a TPCG solve is not split "
+              f"across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2306_00632_amd import problem, tk
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    w = workload(args.workload)
+    ctx = tk.Context(0)
+    op = problem.operator(ctx, w)
+    prec = problem.preconditioner(ctx, w)
+    f = problem.rhs(ctx, w)
+    params = dict(tol=w.tol, eps_min=w.eps_min)
+    for _ in range(args.warmup):
+        x, info = tk.tpcg_solve(ctx, op, prec, f, **params)
+        del x
+    torch.cuda.synchronize()
+    ctx.sync()
+
+    ctx.prof(True)
+    times = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        x, info = tk.tpcg_solve(ctx, op, prec, f, **params)
+        ctx.sync()
+        times.append(time.perf_counter() - t0)
+        last_info = info
+        del x
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    kern = ctx.prof_read()
+    ctx.prof(False)
+
+    ms = [1e3 * t for t in times]
+    kernels = {}
+    for name, d in kern.items():
+        if d["launches"] == 0:
+            continue
+        t = d["ms"] / 1e3
+        kernels[name] = {"launches_per_solve": d["launches"] / args.steps,
+                         "ms_per_solve": d["ms"] / args.steps,
+                         "avg_us": 1e3 * d["ms"] / d["launches"],
+                         "GB_s": d["bytes"] / t / 1e9 if t > 0 else 0.0,
+                         "GFLOP_s": d["flops"] / t / 1e9 if t > 0 else 0.0}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_solve"])
+    dk = kern[dom]
+    if dom in ("band_apply", "fd_forward", "fd_backward", "select_rank"):
+        achieved = dk["bytes"] / dk["launches"] / (dk["ms"] / dk["launches"] / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    else:
+        achieved = dk["flops"] / dk["launches"] / (dk["ms"] / dk["launches"] / 1e3) / 1e12
+        roof = {"bound": "alu" if dom != "dgemm" else "mfma", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": None}
+    roof["kernel"] = dom
+    roof["avg_launch_us"] = 1e3 * dk["ms"] / dk["launches"]
+    mp = kern["band_apply"]
+    mode_gbs = mp["bytes"] / (mp["ms"] / 1e3) / 1e9 if mp["ms"] > 0 else 0.0
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / total,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_el": w.n_el, "p": w.p, "dofs_per_direction": w.n,
+                   "kronecker_terms": len(w.nnz), "rhs_rank": int(np.asarray(problem.rhs_arrays(w)[0]).shape[0]),
+                   "tol": w.tol, "iters": last_info["iters"], "relres": last_info["relres"],
+                   "solution_rank": list(last_info["rank"]), "trel_calls": last_info["trel_calls"]},
+        "latency_ms": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99)),
+                       "min": min(ms), "max": max(ms)},
+        "mode_product_GB_s": mode_gbs,
+        "kernels": kernels,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
+        out["cpu_baseline"] = cpu_baseline(w, last_info["iters"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

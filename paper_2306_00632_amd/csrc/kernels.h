@@ -1,0 +1,75 @@
+// Launch wrappers of the HIP kernels (internal).  All take the stream to
+// launch on; none synchronises.  Matrices are column-major.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tk {
+namespace gpu {
+
+// W[:, t*m + c] = A_t Y[:, c] for the nmat banded matrices (DIA, half-bandwidth p)
+void band_apply(hipStream_t s, int n, int m, int nmat, int p, const double* band,
+                const double* Y, int ldy, double* W, int ldw);
+
+// C = alpha op(A) op(B) + beta C, batched with element strides.
+void dgemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
+           const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
+           double beta, double* C, int ldc, long long sC, int batch = 1);
+
+// Householder QR of up to 3 independent tall matrices (m <= n), one
+// workgroup each.  A (n x m, ld n) is overwritten by the reflectors; R (m x m)
+// and Q (n x m) are written explicitly; tau is scratch of m doubles.
+struct QrJob {
+  double* A;
+  double* R;
+  double* Q;
+  double* tau;
+  int n, m;
+};
+void householder_qr(hipStream_t s, const QrJob* jobs, int njobs);
+
+// Symmetric eigendecomposition G = V diag(w) V^T of an a x a matrix by
+// parallel cyclic Jacobi in one workgroup (LDS-resident for a <= 140).
+// `work` must hold (a+1)^2 doubles when a > 140; the number of sweeps is
+// written to *sweeps (device int, may be null).
+void jacobi_eig(hipStream_t s, double* G, int a, double* V, double* w, double* work, int* sweeps);
+
+// e[j] = sum_i P[i, j]^2 for the a columns of P (rows x a, ld rows)
+void column_energy(hipStream_t s, const double* P, int rows, int a, double* e);
+
+// Rank choice of one ST-HOSVD mode: sort energies descending, keep the
+// smallest s whose discarded tail is <= budget, where budget =
+// eps^2 * norm2 / 3 and norm2 = *norm2_io (if set_norm, norm2 is first set to
+// sum(e)).  Writes sel[0] = s, sel[1..s] = order; tail energy to *disc.
+void select_rank(hipStream_t s, const double* e, int a, double eps, double* norm2_io,
+                 int set_norm, int* sel, double* disc);
+
+// out[:, j] = in[:, idx[j]] for j < s (rows x ., ld rows); idx read from device
+void gather_columns(hipStream_t s, const double* in, int rows, const int* idx, int count,
+                    double* out);
+
+// out = sum over the whole array of x*y (device scalar, accumulated with coef)
+void dot_accumulate(hipStream_t s, const double* x, const double* y, long long n, double coef,
+                    double* out);
+void fill(hipStream_t s, double* x, long long n, double v);
+void scale_copy(hipStream_t s, const double* x, long long n, double a, double* y);
+
+// Low-rank FD transform of one direction (see setup_fd.cpp).
+struct FdDev {
+  int n, n1, n2, N, odd, ke, ket, R;
+  const double* g;       // n1
+  const int* e_idx;      // n * ke
+  const double* e_val;
+  const int* et_idx;     // n1 * ket
+  const double* et_val;
+  const double* v2u2;    // n x n2
+  const double* expD;    // R x n: exp(-alpha_j lam_m / lam_min)
+  const double2* tw;     // 2N/2 twiddles exp(-2 pi i t / 2N)
+};
+// Z (n x r) = U~^T S (n x r, ld lds)
+void fd_forward(hipStream_t s, const FdDev& d, const double* S, int lds, int r, double* Z);
+// Y[:, j*r + c] = U~ D_j Z[:, c] for j < R, c < r  (Y ld = n)
+void fd_backward(hipStream_t s, const FdDev& d, const double* Z, int r, double* Y);
+
+}  // namespace gpu
+}  // namespace tk

@@ -1,0 +1,691 @@
+// HIP kernels for gfx950 (CDNA4, wave64) of the Tucker TPCG library.
+//
+//  band_apply     banded mode products A_(k,t) X_k of eq. (tt_product): one
+//                 workgroup stages a 256-row window of a factor column in LDS
+//                 and applies every 1D matrix of the mode to it (coalesced
+//                 along n, the factor column is read from HBM once).
+//  dgemm          FP64 tiled GEMM (64x64x16 tiles in LDS, 4x4 outputs per
+//                 thread) for the dense core and factor contractions.
+//  householder_qr QR of stacked factors (Algorithm 1, step 1), one workgroup
+//                 per mode, one wavefront per trailing column.
+//  jacobi_eig     parallel cyclic Jacobi (round-robin pairing, two-sided 2x2
+//                 block updates) of the ST-HOSVD Gram matrices, LDS resident.
+//  column_energy, select_rank, gather_columns
+//                 the rank choice of each ST-HOSVD mode from directly
+//                 measured energies ||A^T v_j||^2.
+//  fd_forward / fd_backward
+//                 the low-rank FD transform U~^T and U~ D_j (Algorithm 4,
+//                 Appendix B) as sparse boundary maps and radix-2 Stockham
+//                 FFTs of length 2N in LDS (DST-I for odd p, DST-II/III for
+//                 even p).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <stdexcept>
+#include <string>
+
+#include "kernels.h"
+
+namespace tk {
+namespace gpu {
+
+static void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// block-wide sum; `red` is LDS of >= blockDim.x/64 doubles; result to all threads
+__device__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// banded mode products
+// ---------------------------------------------------------------------------
+
+constexpr int kBandRows = 256;
+
+__global__ __launch_bounds__(kBandRows) void k_band_apply(int n, int m, int nmat, int p,
+                                                          const double* __restrict__ band,
+                                                          const double* __restrict__ Y, int ldy,
+                                                          double* __restrict__ W, int ldw) {
+  extern __shared__ double ys[];
+  const int i0 = blockIdx.x * kBandRows;
+  const int c = blockIdx.y;
+  for (int t = threadIdx.x; t < kBandRows + 2 * p; t += kBandRows) {
+    const int i = i0 - p + t;
+    ys[t] = (i >= 0 && i < n) ? Y[i + (long long)c * ldy] : 0.0;
+  }
+  __syncthreads();
+  const int i = i0 + threadIdx.x;
+  if (i >= n) return;
+  const int nb = 2 * p + 1;
+  for (int t = 0; t < nmat; ++t) {
+    const double* bt = band + (long long)t * nb * n;
+    double acc = 0.0;
+    for (int o = 0; o < nb; ++o) acc += bt[(long long)o * n + i] * ys[threadIdx.x + o];
+    W[i + (long long)(t * m + c) * ldw] = acc;
+  }
+}
+
+void band_apply(hipStream_t s, int n, int m, int nmat, int p, const double* band,
+                const double* Y, int ldy, double* W, int ldw) {
+  if (n <= 0 || m <= 0 || nmat <= 0) return;
+  dim3 grid((n + kBandRows - 1) / kBandRows, m);
+  const size_t lds = sizeof(double) * (kBandRows + 2 * p);
+  hipLaunchKernelGGL(k_band_apply, grid, dim3(kBandRows), lds, s, n, m, nmat, p, band, Y, ldy, W, ldw);
+  check_launch("band_apply");
+}
+
+// ---------------------------------------------------------------------------
+// FP64 GEMM
+// ---------------------------------------------------------------------------
+
+constexpr int BM = 64, BN = 64, BK = 16;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha,
+                                               const double* __restrict__ A, int lda, long long sA,
+                                               const double* __restrict__ B, int ldb, long long sB,
+                                               double beta, double* __restrict__ C, int ldc,
+                                               long long sC) {
+  __shared__ double As[BK][BM + 1];
+  __shared__ double Bs[BK][BN + 1];
+  A += sA * blockIdx.z;
+  B += sB * blockIdx.z;
+  C += sC * blockIdx.z;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int row0 = blockIdx.x * BM, col0 = blockIdx.y * BN;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    // A tile: op(A)[row0 + i][k0 + kk]
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int e = threadIdx.x + 256 * l;
+      int i, kk;
+      if (!TA) { i = e & (BM - 1); kk = e >> 6; } else { kk = e & (BK - 1); i = e >> 4; }
+      const int gr = row0 + i, gk = k0 + kk;
+      double v = 0.0;
+      if (gr < M && gk < K) v = TA ? A[gk + (long long)gr * lda] : A[gr + (long long)gk * lda];
+      As[kk][i] = v;
+    }
+    // B tile: op(B)[k0 + kk][col0 + j]
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int e = threadIdx.x + 256 * l;
+      int j, kk;
+      if (!TB) { kk = e & (BK - 1); j = e >> 4; } else { j = e & (BN - 1); kk = e >> 6; }
+      const int gc = col0 + j, gk = k0 + kk;
+      double v = 0.0;
+      if (gc < N && gk < K) v = TB ? B[gc + (long long)gk * ldb] : B[gk + (long long)gc * ldb];
+      Bs[kk][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tx + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][ty + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int gc = col0 + ty + 16 * j;
+    if (gc >= N) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int gr = row0 + tx + 16 * i;
+      if (gr >= M) continue;
+      double* cp = C + gr + (long long)gc * ldc;
+      *cp = (beta == 0.0) ? alpha * acc[i][j] : alpha * acc[i][j] + beta * (*cp);
+    }
+  }
+}
+
+void dgemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
+           const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
+           double beta, double* C, int ldc, long long sC, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  if (K <= 0) {
+    if (beta == 1.0) return;
+    // C = beta C
+    for (int b = 0; b < batch; ++b)
+      for (int j = 0; j < N; ++j) scale_copy(s, C + sC * b + (long long)j * ldc, M, beta, C + sC * b + (long long)j * ldc);
+    return;
+  }
+  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, batch);
+  if (!ta && !tb) hipLaunchKernelGGL((k_dgemm<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  else if (ta && !tb) hipLaunchKernelGGL((k_dgemm<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  else if (!ta && tb) hipLaunchKernelGGL((k_dgemm<false, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  else hipLaunchKernelGGL((k_dgemm<true, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  check_launch("dgemm");
+}
+
+// ---------------------------------------------------------------------------
+// Householder QR
+// ---------------------------------------------------------------------------
+
+struct QrJobs {
+  QrJob j[3];
+};
+
+constexpr int kQrThreads = 512;
+
+__global__ __launch_bounds__(kQrThreads) void k_householder_qr(QrJobs jobs) {
+  const QrJob job = jobs.j[blockIdx.x];
+  double* A = job.A;
+  const int n = job.n, m = job.m;
+  __shared__ double red[kQrThreads / 64];
+  __shared__ double s_tau;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kQrThreads / 64;
+  for (int e = threadIdx.x; e < m * m; e += kQrThreads) job.R[e] = 0.0;
+  for (int j = 0; j < m; ++j) {
+    double part = 0.0;
+    for (int i = j + threadIdx.x; i < n; i += kQrThreads) {
+      const double v = A[i + (long long)j * n];
+      part += v * v;
+    }
+    const double s2 = block_sum(part, red);
+    if (threadIdx.x == 0) {
+      const double x0 = A[j + (long long)j * n];
+      const double nrm = sqrt(s2);
+      double tau = 0.0, alpha = 0.0;
+      if (nrm > 0.0) {
+        alpha = (x0 >= 0.0) ? -nrm : nrm;
+        const double v0 = x0 - alpha;
+        A[j + (long long)j * n] = v0;
+        const double vtv = s2 - x0 * x0 + v0 * v0;
+        tau = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+      }
+      job.R[j + (long long)j * m] = alpha;
+      job.tau[j] = tau;
+      s_tau = tau;
+    }
+    __syncthreads();
+    const double tau = s_tau;
+    for (int c = j + 1 + wid; c < m; c += nw) {
+      double d = 0.0;
+      if (tau != 0.0)
+        for (int i = j + lane; i < n; i += 64) d += A[i + (long long)j * n] * A[i + (long long)c * n];
+      d = wave_sum(d) * tau;
+      if (tau != 0.0)
+        for (int i = j + lane; i < n; i += 64) A[i + (long long)c * n] -= d * A[i + (long long)j * n];
+      if (lane == 0) job.R[j + (long long)c * m] = A[j + (long long)c * n];
+    }
+    __syncthreads();
+  }
+  // Q = H_0 ... H_{m-1} [I; 0]
+  for (long long e = threadIdx.x; e < (long long)n * m; e += kQrThreads) {
+    const int i = int(e % n), c = int(e / n);
+    job.Q[e] = (i == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = m - 1; j >= 0; --j) {
+    const double tau = job.tau[j];
+    if (tau != 0.0) {
+      for (int c = j + wid; c < m; c += nw) {
+        double d = 0.0;
+        for (int i = j + lane; i < n; i += 64) d += A[i + (long long)j * n] * job.Q[i + (long long)c * n];
+        d = wave_sum(d) * tau;
+        for (int i = j + lane; i < n; i += 64) job.Q[i + (long long)c * n] -= d * A[i + (long long)j * n];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+void householder_qr(hipStream_t s, const QrJob* jobs, int njobs) {
+  if (njobs <= 0) return;
+  QrJobs js;
+  for (int i = 0; i < njobs; ++i) js.j[i] = jobs[i];
+  hipLaunchKernelGGL(k_householder_qr, dim3(njobs), dim3(kQrThreads), 0, s, js);
+  check_launch("householder_qr");
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi eigensolver
+// ---------------------------------------------------------------------------
+
+constexpr int kJacLdsMax = 140;
+constexpr int kJacThreads = 1024;
+
+__global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict__ G, int a,
+                                                        double* __restrict__ V,
+                                                        double* __restrict__ w,
+                                                        double* __restrict__ work,
+                                                        int* __restrict__ sweeps_out) {
+  extern __shared__ double smem[];
+  const int P = (a + 1) & ~1;
+  const int H = P / 2;
+  const bool in_lds = P <= kJacLdsMax;
+  double* S = in_lds ? smem : work;
+  double* cs = in_lds ? smem + P * P : smem;
+  double* sn = cs + H;
+  int* pp = reinterpret_cast<int*>(sn + H);
+  int* qq = pp + H;
+  __shared__ int rotated;
+  __shared__ double dmax;
+  for (int e = threadIdx.x; e < P * P; e += kJacThreads) {
+    const int i = e % P, j = e / P;
+    S[e] = (i < a && j < a) ? G[i + (long long)j * a] : 0.0;
+  }
+  for (long long e = threadIdx.x; e < (long long)a * a; e += kJacThreads)
+    V[e] = ((e % a) == (e / a)) ? 1.0 : 0.0;
+  __syncthreads();
+  int sweep = 0;
+  for (; sweep < 40; ++sweep) {
+    if (threadIdx.x == 0) {
+      double dm = 0.0;
+      for (int i = 0; i < a; ++i) dm = fmax(dm, fabs(S[i + i * P]));
+      dmax = dm;
+      rotated = 0;
+    }
+    __syncthreads();
+    const double floor_abs = 1e-16 * dmax;
+    for (int r = 0; r < P - 1; ++r) {
+      for (int t = threadIdx.x; t < H; t += kJacThreads) {
+        int p, q;
+        if (t == 0) { p = r % (P - 1); q = P - 1; }
+        else { p = (r + t) % (P - 1); q = (r - t + P - 1) % (P - 1); }
+        if (p > q) { const int x = p; p = q; q = x; }
+        double c = 1.0, s = 0.0;
+        const double apq = S[p + q * P];
+        if (q < a && apq != 0.0) {
+          const double app = S[p + p * P], aqq = S[q + q * P];
+          if (!(fabs(apq) <= 1e-15 * sqrt(fabs(app * aqq)) || fabs(apq) <= floor_abs)) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+            rotated = 1;
+          }
+        }
+        cs[t] = c;
+        sn[t] = s;
+        pp[t] = p;
+        qq[t] = q;
+      }
+      __syncthreads();
+      // two-sided update of the 2x2 blocks (pair t1 rows, pair t2 columns)
+      for (int e = threadIdx.x; e < H * H; e += kJacThreads) {
+        const int t1 = e % H, t2 = e / H;
+        const double c1 = cs[t1], s1 = sn[t1], c2 = cs[t2], s2 = sn[t2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const int p1 = pp[t1], q1 = qq[t1], p2 = pp[t2], q2 = qq[t2];
+        double xpp = S[p1 + p2 * P], xpq = S[p1 + q2 * P], xqp = S[q1 + p2 * P], xqq = S[q1 + q2 * P];
+        // rows: J1^T X
+        double ypp = c1 * xpp - s1 * xqp, ypq = c1 * xpq - s1 * xqq;
+        double yqp = s1 * xpp + c1 * xqp, yqq = s1 * xpq + c1 * xqq;
+        // columns: (J1^T X) J2
+        S[p1 + p2 * P] = c2 * ypp - s2 * ypq;
+        S[p1 + q2 * P] = s2 * ypp + c2 * ypq;
+        S[q1 + p2 * P] = c2 * yqp - s2 * yqq;
+        S[q1 + q2 * P] = s2 * yqp + c2 * yqq;
+      }
+      for (int e = threadIdx.x; e < a * H; e += kJacThreads) {
+        const int i = e % a, t2 = e / a;
+        const double s2 = sn[t2];
+        if (s2 == 0.0) continue;
+        const int p2 = pp[t2], q2 = qq[t2];
+        if (q2 >= a) continue;
+        const double c2 = cs[t2];
+        const double vp = V[i + (long long)p2 * a], vq = V[i + (long long)q2 * a];
+        V[i + (long long)p2 * a] = c2 * vp - s2 * vq;
+        V[i + (long long)q2 * a] = s2 * vp + c2 * vq;
+      }
+      __syncthreads();
+    }
+    if (rotated == 0) break;
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < a; i += kJacThreads) w[i] = S[i + i * P];
+  if (threadIdx.x == 0 && sweeps_out) *sweeps_out = sweep + 1;
+}
+
+void jacobi_eig(hipStream_t s, double* G, int a, double* V, double* w, double* work, int* sweeps) {
+  if (a <= 0) return;
+  const int P = (a + 1) & ~1;
+  size_t lds;
+  if (P <= kJacLdsMax) lds = sizeof(double) * (P * P + P) + sizeof(int) * P;
+  else lds = sizeof(double) * P + sizeof(int) * P;
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(kJacThreads), lds, s, G, a, V, w, work, sweeps);
+  check_launch("jacobi_eig");
+}
+
+// ---------------------------------------------------------------------------
+// rank selection
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_column_energy(const double* __restrict__ P, int rows,
+                                                       double* __restrict__ e) {
+  __shared__ double red[4];
+  const double* col = P + (long long)blockIdx.x * rows;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < rows; i += 256) s += col[i] * col[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) e[blockIdx.x] = s;
+}
+
+void column_energy(hipStream_t s, const double* P, int rows, int a, double* e) {
+  if (a <= 0) return;
+  hipLaunchKernelGGL(k_column_energy, dim3(a), dim3(256), 0, s, P, rows, e);
+  check_launch("column_energy");
+}
+
+constexpr int kSelMax = 2048;
+
+__global__ __launch_bounds__(1024) void k_select(const double* __restrict__ e, int a, double eps,
+                                                 double* norm2_io, int set_norm, int* sel,
+                                                 double* disc) {
+  __shared__ double key[kSelMax];
+  __shared__ int idx[kSelMax];
+  __shared__ double red[16];
+  int P2 = 1;
+  while (P2 < a) P2 <<= 1;
+  double part = 0.0;
+  for (int i = threadIdx.x; i < P2; i += 1024) {
+    key[i] = (i < a) ? e[i] : -1.0;
+    idx[i] = i;
+    if (i < a) part += e[i];
+  }
+  const double tot = block_sum(part, red);
+  __syncthreads();
+  // bitonic sort, descending by key (ties: ascending index)
+  for (int k = 2; k <= P2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P2; i += 1024) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool desc = ((i & k) == 0);
+          const double ki = key[i], kl = key[l];
+          const int ii = idx[i], il = idx[l];
+          const bool i_first = (ki > kl) || (ki == kl && ii < il);
+          const bool swap = desc ? !i_first : i_first;
+          if (swap) {
+            key[i] = kl; key[l] = ki;
+            idx[i] = il; idx[l] = ii;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    double norm2 = set_norm ? tot : *norm2_io;
+    if (set_norm) *norm2_io = norm2;
+    const double budget = eps * eps * norm2 / 3.0;
+    double tail = 0.0;
+    int s = a;
+    for (int i = a - 1; i >= 0; --i) {
+      const double v = key[i] > 0.0 ? key[i] : 0.0;
+      if (tail + v <= budget) { tail += v; s = i; }
+      else break;
+    }
+    sel[0] = s;
+    *disc = tail;
+  }
+  __syncthreads();
+  const int s = sel[0];
+  for (int i = threadIdx.x; i < s; i += 1024) sel[1 + i] = idx[i];
+}
+
+void select_rank(hipStream_t s, const double* e, int a, double eps, double* norm2_io,
+                 int set_norm, int* sel, double* disc) {
+  if (a > kSelMax) throw std::runtime_error("select_rank: more than 2048 columns");
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, e, a, eps, norm2_io, set_norm, sel, disc);
+  check_launch("select_rank");
+}
+
+__global__ __launch_bounds__(256) void k_gather_columns(const double* __restrict__ in, int rows,
+                                                        const int* __restrict__ idx,
+                                                        double* __restrict__ out) {
+  const int j = blockIdx.y;
+  const int src = idx[j];
+  const double* col = in + (long long)src * rows;
+  double* dst = out + (long long)j * rows;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < rows; i += 256 * gridDim.x) dst[i] = col[i];
+}
+
+void gather_columns(hipStream_t s, const double* in, int rows, const int* idx, int count,
+                    double* out) {
+  if (count <= 0 || rows <= 0) return;
+  const int bx = std::min((rows + 255) / 256, 64);
+  hipLaunchKernelGGL(k_gather_columns, dim3(bx, count), dim3(256), 0, s, in, rows, idx, out);
+  check_launch("gather_columns");
+}
+
+// ---------------------------------------------------------------------------
+// reductions and elementwise helpers
+// ---------------------------------------------------------------------------
+
+constexpr int kRedBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ x,
+                                                     const double* __restrict__ y, long long n,
+                                                     double* __restrict__ part) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) s += x[i] * y[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ part, int np,
+                                                   double coef, double* out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) s += part[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) *out += coef * s;
+}
+
+void dot_accumulate(hipStream_t s, const double* x, const double* y, long long n, double coef,
+                    double* out) {
+  // out is followed by kRedBlocks doubles of scratch (see runtime)
+  if (n <= 0) return;
+  const int nb = (int)std::min<long long>(kRedBlocks, (n + 255) / 256);
+  double* part = out + 1;
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, s, x, y, n, part);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, part, nb, coef, out);
+  check_launch("dot_accumulate");
+}
+
+__global__ void k_fill(double* x, long long n, double v) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) x[i] = v;
+}
+
+void fill(hipStream_t s, double* x, long long n, double v) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<long long>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, x, n, v);
+  check_launch("fill");
+}
+
+__global__ void k_scale_copy(const double* x, long long n, double a, double* y) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) y[i] = a * x[i];
+}
+
+void scale_copy(hipStream_t s, const double* x, long long n, double a, double* y) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<long long>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_scale_copy, dim3(nb), dim3(256), 0, s, x, n, a, y);
+  check_launch("scale_copy");
+}
+
+// ---------------------------------------------------------------------------
+// low-rank FD transform: FFT-based DSTs in LDS
+// ---------------------------------------------------------------------------
+
+constexpr int kFdThreads = 256;
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Radix-2 Stockham FFT of length L (power of two) in LDS; `sign` = -1 forward
+// (exp(-2 pi i)), +1 inverse (unnormalised).  Returns the buffer holding
+// the result.
+__device__ double2* fft_lds(double2* in, double2* out, const double2* tw, int L, int sign) {
+  const int half = L >> 1;
+  for (int Ns = 1; Ns < L; Ns <<= 1) {
+    const int step = half / Ns;
+    for (int j = threadIdx.x; j < half; j += blockDim.x) {
+      const int k = j & (Ns - 1);
+      double2 w = tw[k * step];
+      if (sign > 0) w.y = -w.y;
+      const double2 a = in[j];
+      const double2 b = cmul(in[j + half], w);
+      const int idx = 2 * (j - k) + k;
+      out[idx] = make_double2(a.x + b.x, a.y + b.y);
+      out[idx + Ns] = make_double2(a.x - b.x, a.y - b.y);
+    }
+    __syncthreads();
+    double2* t = in;
+    in = out;
+    out = t;
+  }
+  return in;
+}
+
+__global__ __launch_bounds__(kFdThreads) void k_fd_forward(FdDev d, const double* __restrict__ S,
+                                                           int lds_, double* __restrict__ Z) {
+  extern __shared__ double2 sm2[];
+  const int N = d.N, L = 2 * N;
+  double2* b0 = sm2;
+  double2* b1 = b0 + L;
+  double2* tw = b1 + L;
+  double* sv = reinterpret_cast<double*>(tw + N);
+  double* red = sv + d.n;
+  const int c = blockIdx.x;
+  const double* col = S + (long long)c * lds_;
+  for (int i = threadIdx.x; i < d.n; i += kFdThreads) sv[i] = col[i];
+  for (int i = threadIdx.x; i < N; i += kFdThreads) tw[i] = d.tw[i];
+  for (int i = threadIdx.x; i < L; i += kFdThreads) b0[i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  // t = E^T s, laid out as the odd extension of the DST input
+  for (int mm = threadIdx.x; mm < d.n1; mm += kFdThreads) {
+    double t = 0.0;
+    for (int k = 0; k < d.ket; ++k) {
+      const int src = d.et_idx[mm * d.ket + k];
+      if (src >= 0) t += d.et_val[mm * d.ket + k] * sv[src];
+    }
+    if (d.odd) {            // y[m+1] = t, y[2N-m-1] = -t   (DST-I)
+      b0[mm + 1].x = t;
+      b0[L - mm - 1].x = -t;
+    } else {                // y[m] = t, y[2N-1-m] = -t      (DST-II)
+      b0[mm].x = t;
+      b0[L - 1 - mm].x = -t;
+    }
+  }
+  __syncthreads();
+  double2* Y = fft_lds(b0, b1, tw, L, -1);
+  double* zc = Z + (long long)c * d.n;
+  for (int mm = threadIdx.x; mm < d.n1; mm += kFdThreads) {
+    const int k = mm + 1;
+    double u;
+    if (d.odd) {
+      u = -0.5 * Y[k].y;
+    } else {
+      const double ang = -3.14159265358979323846 * k / (2.0 * N);
+      double sa, ca;
+      sincos(ang, &sa, &ca);
+      // Im(e^{i ang} Y[k])
+      u = -0.5 * (ca * Y[k].y + sa * Y[k].x);
+    }
+    zc[mm] = d.g[mm] * u;
+  }
+  for (int a = 0; a < d.n2; ++a) {
+    double part = 0.0;
+    for (int i = threadIdx.x; i < d.n; i += kFdThreads) part += d.v2u2[i + (long long)a * d.n] * sv[i];
+    const double t = block_sum(part, red);
+    if (threadIdx.x == 0) zc[d.n1 + a] = t;
+  }
+}
+
+__global__ __launch_bounds__(kFdThreads) void k_fd_backward(FdDev d, const double* __restrict__ Z,
+                                                            int r, double* __restrict__ Yout) {
+  extern __shared__ double2 sm2[];
+  const int N = d.N, L = 2 * N;
+  double2* b0 = sm2;
+  double2* b1 = b0 + L;
+  double2* tw = b1 + L;
+  double* cv = reinterpret_cast<double*>(tw + N);
+  double* w2 = cv + d.n1;
+  const int c = blockIdx.x, j = blockIdx.y;
+  const double* zc = Z + (long long)c * d.n;
+  const double* ej = d.expD + (long long)j * d.n;
+  for (int i = threadIdx.x; i < N; i += kFdThreads) tw[i] = d.tw[i];
+  for (int i = threadIdx.x; i < L; i += kFdThreads) b0[i] = make_double2(0.0, 0.0);
+  for (int a = threadIdx.x; a < d.n2; a += kFdThreads) w2[a] = ej[d.n1 + a] * zc[d.n1 + a];
+  __syncthreads();
+  for (int mm = threadIdx.x; mm < d.n1; mm += kFdThreads) {
+    const double wv = ej[mm] * d.g[mm] * zc[mm];
+    if (d.odd) {
+      b0[mm + 1].x = wv;
+      b0[L - mm - 1].x = -wv;
+    } else {                // c[k] = w_{k-1} e^{i pi k / 2N}, k = 1..N
+      const int k = mm + 1;
+      double sa, ca;
+      sincos(3.14159265358979323846 * k / (2.0 * N), &sa, &ca);
+      b0[k] = make_double2(wv * ca, wv * sa);
+    }
+  }
+  __syncthreads();
+  double2* F = fft_lds(b0, b1, tw, L, d.odd ? -1 : +1);
+  for (int mm = threadIdx.x; mm < d.n1; mm += kFdThreads)
+    cv[mm] = d.odd ? -0.5 * F[mm + 1].y : F[mm].y;
+  __syncthreads();
+  double* yc = Yout + (long long)(j * r + c) * d.n;
+  for (int l = threadIdx.x; l < d.n; l += kFdThreads) {
+    double acc = 0.0;
+    for (int k = 0; k < d.ke; ++k) {
+      const int src = d.e_idx[l * d.ke + k];
+      if (src >= 0) acc += d.e_val[l * d.ke + k] * cv[src];
+    }
+    for (int a = 0; a < d.n2; ++a) acc += d.v2u2[l + (long long)a * d.n] * w2[a];
+    yc[l] = acc;
+  }
+}
+
+static size_t fd_lds_bytes(const FdDev& d) {
+  return sizeof(double2) * (4 * d.N + d.N) + sizeof(double) * (d.n + d.n1 + d.n2 + 16);
+}
+
+void fd_forward(hipStream_t s, const FdDev& d, const double* S, int lds_, int r, double* Z) {
+  if (r <= 0) return;
+  hipLaunchKernelGGL(k_fd_forward, dim3(r), dim3(kFdThreads), fd_lds_bytes(d), s, d, S, lds_, Z);
+  check_launch("fd_forward");
+}
+
+void fd_backward(hipStream_t s, const FdDev& d, const double* Z, int r, double* Y) {
+  if (r <= 0 || d.R <= 0) return;
+  hipLaunchKernelGGL(k_fd_backward, dim3(r, d.R), dim3(kFdThreads), fd_lds_bytes(d), s, d, Z, r, Y);
+  check_launch("fd_backward");
+}
+
+}  // namespace gpu
+}  // namespace tk

@@ -1,0 +1,1194 @@
+// Runtime of the Tucker TPCG library: context, stream-ordered caching
+// allocator, lazy Tucker tensors, operator and preconditioner objects,
+// relative/dynamic truncation, Tucker scalar products, TPCG, and the C ABI
+// declared in include/tk.h.
+//
+// Paper references: Sec. 2.3 (Tucker format, eq. tt_product, scalar product,
+// sums), Sec. 4.1 (Algorithms 1 and 2), Sec. 4.2 (Algorithm 4), Sec. 4.3
+// (Algorithm 5, eq. rel_tol_iterates), Sec. 5 (default parameters).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/tk.h"
+#include "kernels.h"
+#include "tk_internal.h"
+
+namespace tk {
+
+struct Error : std::runtime_error {
+  tk_status code;
+  Error(tk_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      throw ::tk::Error(TK_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// stream-ordered caching allocator: every kernel of a context runs on one
+// stream, so a buffer returned to the cache may be handed out again at once
+// (later work on the stream is ordered after earlier uses).
+// ---------------------------------------------------------------------------
+
+class Pool {
+ public:
+  explicit Pool(int dev) : dev_(dev) {}
+  ~Pool() { trim(); }
+  void* get(size_t bytes) {
+    const size_t b = bucket(bytes);
+    auto& fl = free_[b];
+    if (!fl.empty()) {
+      void* p = fl.back();
+      fl.pop_back();
+      return p;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      if (hipMalloc(&p, b) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(TK_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+      }
+    }
+    return p;
+  }
+  void put(void* p, size_t bytes) {
+    if (p) free_[bucket(bytes)].push_back(p);
+  }
+  void trim() {
+    for (auto& kv : free_)
+      for (void* p : kv.second) (void)hipFree(p);
+    free_.clear();
+  }
+
+ private:
+  static size_t bucket(size_t bytes) {
+    size_t b = 256;
+    while (b < bytes) b <<= 1;
+    return b;
+  }
+  int dev_;
+  std::map<size_t, std::vector<void*>> free_;
+};
+
+struct Buf {
+  double* p = nullptr;
+  size_t bytes = 0;
+  Pool* pool = nullptr;
+  ~Buf() {
+    if (pool) pool->put(p, bytes);
+  }
+};
+using BufP = std::shared_ptr<Buf>;
+
+}  // namespace tk
+
+// ---------------------------------------------------------------------------
+// public object types
+// ---------------------------------------------------------------------------
+
+namespace tk {
+// kernel families timed by the optional HIP-event instrumentation
+enum ProfKind { PK_BAND = 0, PK_GEMM, PK_QR, PK_JACOBI, PK_SELECT, PK_FD_FWD, PK_FD_BWD, PK_MISC, PK_N };
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+  double bytes, flops;
+};
+}  // namespace tk
+
+struct tk_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::unique_ptr<tk::Pool> pool;
+  std::string last_error;
+  tk::BufP scal;  // device scalars: [0] accumulator + 256 scratch, [300..] misc
+  tk::BufP sel;   // rank-selection output (ints)
+  // instrumentation (off by default)
+  bool prof = false;
+  std::vector<tk::ProfRec> recs;
+  std::vector<hipEvent_t> evpool;
+  double p_ms[tk::PK_N] = {}, p_bytes[tk::PK_N] = {}, p_flops[tk::PK_N] = {};
+  long long p_n[tk::PK_N] = {};
+};
+
+namespace tk {
+
+struct Block {
+  double c = 1.0;
+  BufP core;  // r0 x r1 x r2
+  int r[3] = {0, 0, 0};
+  int off[3] = {0, 0, 0};
+};
+
+}  // namespace tk
+
+struct tk_tucker {
+  int n[3] = {0, 0, 0};
+  int m[3] = {0, 0, 0};
+  tk::BufP U[3];  // n_k x m_k
+  std::vector<tk::Block> blocks;
+};
+
+struct tk_op {
+  int p = 0;
+  int n[3] = {0, 0, 0};
+  int nmat[3] = {0, 0, 0};
+  tk::BufP band[3];
+  std::vector<tk_core_nz> nz;
+};
+
+struct tk_prec {
+  int R = 0;
+  double lam_min = 0, lam_max = 0, err = 0, err_prev = 0;
+  std::vector<double> alpha, omega;
+  tk::FdDirection dir[3];
+  tk::BufP g[3], e_val[3], et_val[3], v2u2[3], expD[3], tw[3];
+  tk::BufP e_idx[3], et_idx[3];  // stored as ints inside double buffers
+  tk::gpu::FdDev dev[3];
+};
+
+namespace tk {
+
+static BufP alloc(tk_ctx* ctx, size_t count) {
+  auto b = std::make_shared<Buf>();
+  b->bytes = std::max<size_t>(count, 1) * sizeof(double);
+  b->p = static_cast<double*>(ctx->pool->get(b->bytes));
+  b->pool = ctx->pool.get();
+  return b;
+}
+
+static void sync(tk_ctx* ctx) { HIPCHK(hipStreamSynchronize(ctx->stream)); }
+
+static void d2d(tk_ctx* ctx, double* dst, const double* src, size_t count) {
+  if (count) HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+}
+
+static void h2d(tk_ctx* ctx, double* dst, const double* src, size_t count) {
+  if (count) {
+    HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    sync(ctx);  // host memory may be released by the caller after return
+  }
+}
+
+static std::vector<double> d2h(tk_ctx* ctx, const double* src, size_t count) {
+  std::vector<double> out(count);
+  if (count) {
+    HIPCHK(hipMemcpyAsync(out.data(), src, count * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+  }
+  return out;
+}
+
+static long long prod3(const int r[3]) { return (long long)r[0] * r[1] * r[2]; }
+
+// ---------------------------------------------------------------------------
+// instrumentation: events around launches of one kernel family
+// ---------------------------------------------------------------------------
+
+static hipEvent_t get_event(tk_ctx* ctx) {
+  if (!ctx->evpool.empty()) {
+    hipEvent_t e = ctx->evpool.back();
+    ctx->evpool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
+static void prof_flush(tk_ctx* ctx) {
+  for (auto& r : ctx->recs) {
+    HIPCHK(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    ctx->p_ms[r.kind] += ms;
+    ctx->p_bytes[r.kind] += r.bytes;
+    ctx->p_flops[r.kind] += r.flops;
+    ctx->p_n[r.kind] += 1;
+    ctx->evpool.push_back(r.a);
+    ctx->evpool.push_back(r.b);
+  }
+  ctx->recs.clear();
+}
+
+struct Prof {
+  tk_ctx* ctx;
+  ProfRec r{};
+  Prof(tk_ctx* c, int kind, double bytes, double flops) : ctx(c) {
+    if (!ctx->prof) return;
+    r.kind = kind;
+    r.bytes = bytes;
+    r.flops = flops;
+    r.a = get_event(ctx);
+    r.b = get_event(ctx);
+    HIPCHK(hipEventRecord(r.a, ctx->stream));
+  }
+  ~Prof() {
+    if (!ctx->prof) return;
+    if (hipEventRecord(r.b, ctx->stream) != hipSuccess) {
+      ctx->evpool.push_back(r.a);
+      ctx->evpool.push_back(r.b);
+      return;
+    }
+    ctx->recs.push_back(r);
+    if (ctx->recs.size() > 8192) {
+      try {
+        prof_flush(ctx);
+      } catch (...) {
+      }
+    }
+  }
+};
+
+static void gemm(tk_ctx* ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
+                 const double* B, int ldb, double beta, double* C, int ldc) {
+  Prof pr(ctx, PK_GEMM, 8.0 * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1)),
+          2.0 * M * N * (double)K);
+  gpu::dgemm(ctx->stream, ta, tb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Tucker objects
+// ---------------------------------------------------------------------------
+
+static tk_tucker* make_plain(tk_ctx* ctx, const int n[3], const int r[3]) {
+  auto* t = new tk_tucker;
+  for (int k = 0; k < 3; ++k) {
+    t->n[k] = n[k];
+    t->m[k] = r[k];
+    t->U[k] = alloc(ctx, (size_t)n[k] * r[k]);
+  }
+  Block b;
+  b.core = alloc(ctx, (size_t)prod3(r));
+  for (int k = 0; k < 3; ++k) b.r[k] = r[k];
+  t->blocks.push_back(b);
+  return t;
+}
+
+// lazy a*x + b*y: concatenated factors, blocks shifted (Sec. 2.3 sum)
+static tk_tucker* lin_comb(tk_ctx* ctx, double a, const tk_tucker* x, double b, const tk_tucker* y) {
+  for (int k = 0; k < 3; ++k)
+    if (x->n[k] != y->n[k]) throw Error(TK_EINVAL, "sum of Tucker tensors of different sizes");
+  auto* t = new tk_tucker;
+  for (int k = 0; k < 3; ++k) {
+    t->n[k] = x->n[k];
+    t->m[k] = x->m[k] + y->m[k];
+    t->U[k] = alloc(ctx, (size_t)t->n[k] * t->m[k]);
+    d2d(ctx, t->U[k]->p, x->U[k]->p, (size_t)x->n[k] * x->m[k]);
+    d2d(ctx, t->U[k]->p + (size_t)x->n[k] * x->m[k], y->U[k]->p, (size_t)y->n[k] * y->m[k]);
+  }
+  for (const auto& bl : x->blocks) {
+    Block c = bl;
+    c.c *= a;
+    t->blocks.push_back(c);
+  }
+  for (const auto& bl : y->blocks) {
+    Block c = bl;
+    c.c *= b;
+    for (int k = 0; k < 3; ++k) c.off[k] += x->m[k];
+    t->blocks.push_back(c);
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// scalar products (Sec. 2.3): <X, Y> = vec(Gx)^T vec(Gy x_1 W1 x_2 W2 x_3 W3),
+// W_k = X_k^T Y_k; lazy sums are expanded over pairs of blocks.
+// ---------------------------------------------------------------------------
+
+// T (r0 x r1 x r2 tensor, ld as matrix r0 x r1r2) x_1 M0 x_2 M1 x_3 M2 by three
+// GEMMs that each contract the leading mode and rotate it to the back:
+// (a x bc) -> (bc x a') = T^T M^T.  M_k is s_k x r_k with leading dim ldm[k].
+static BufP multi_mode_product(tk_ctx* ctx, const double* T, const int r[3], const double* const M[3],
+                               const int s[3], const int ldm[3]) {
+  int dims[3] = {r[0], r[1], r[2]};
+  const double* cur = T;
+  BufP hold;
+  for (int k = 0; k < 3; ++k) {
+    const int a = dims[0], bc = dims[1] * dims[2];
+    BufP out = alloc(ctx, (size_t)bc * s[k]);
+    gemm(ctx, true, true, bc, s[k], a, 1.0, cur, a, M[k], ldm[k], 0.0, out->p, bc);
+    hold = out;
+    cur = out->p;
+    dims[0] = dims[1];
+    dims[1] = dims[2];
+    dims[2] = s[k];
+  }
+  return hold;  // s0 x s1 x s2
+}
+
+static double dot(tk_ctx* ctx, const tk_tucker* x, const tk_tucker* y) {
+  for (int k = 0; k < 3; ++k)
+    if (x->n[k] != y->n[k]) throw Error(TK_EINVAL, "dot of Tucker tensors of different sizes");
+  double* acc = ctx->scal->p;
+  gpu::fill(ctx->stream, acc, 1, 0.0);
+  bool any = false;
+  BufP W[3];
+  for (int k = 0; k < 3; ++k) {
+    if (x->m[k] == 0 || y->m[k] == 0) return 0.0;
+    W[k] = alloc(ctx, (size_t)x->m[k] * y->m[k]);  // m_x x m_y
+    gemm(ctx, true, false, x->m[k], y->m[k], x->n[k], 1.0, x->U[k]->p, x->n[k], y->U[k]->p, y->n[k], 0.0, W[k]->p, x->m[k]);
+  }
+  for (const auto& bx : x->blocks)
+    for (const auto& by : y->blocks) {
+      if (prod3(bx.r) == 0 || prod3(by.r) == 0) continue;
+      const double* M[3];
+      int ldm[3];
+      for (int k = 0; k < 3; ++k) {
+        M[k] = W[k]->p + bx.off[k] + (size_t)by.off[k] * x->m[k];
+        ldm[k] = x->m[k];
+      }
+      BufP T = multi_mode_product(ctx, by.core->p, by.r, M, bx.r, ldm);
+      gpu::dot_accumulate(ctx->stream, bx.core->p, T->p, prod3(bx.r), bx.c * by.c, acc);
+      any = true;
+    }
+  if (!any) return 0.0;
+  auto h = d2h(ctx, acc, 1);
+  return h[0];
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1 (relative truncation), steps 1-2 kept for reuse by Algorithm 2
+// ---------------------------------------------------------------------------
+
+struct TruncPrep {
+  int n[3];
+  int q[3];         // rows of R_k = columns of Q_k
+  bool ident[3];    // Q_k = I (when m_k >= n_k, R_k = Y_k)
+  BufP Q[3];        // n_k x q_k (unless ident)
+  BufP Z;           // q0 x q1 x q2
+  double norm2 = 0; // ||Z||^2 (set by the first ST-HOSVD mode)
+};
+
+static TruncPrep truncate_prepare(tk_ctx* ctx, const tk_tucker* y) {
+  TruncPrep P;
+  BufP R[3];
+  gpu::QrJob jobs[3];
+  int nj = 0;
+  std::vector<BufP> keep;
+  for (int k = 0; k < 3; ++k) {
+    P.n[k] = y->n[k];
+    const int n = y->n[k], m = y->m[k];
+    if (m >= n) {
+      P.ident[k] = true;
+      P.q[k] = n;
+      R[k] = y->U[k];  // R_k = Y_k (n x m)
+    } else {
+      P.ident[k] = false;
+      P.q[k] = m;
+      BufP A = alloc(ctx, (size_t)n * m);
+      d2d(ctx, A->p, y->U[k]->p, (size_t)n * m);
+      R[k] = alloc(ctx, (size_t)m * m);
+      P.Q[k] = alloc(ctx, (size_t)n * m);
+      BufP tau = alloc(ctx, (size_t)m);
+      keep.push_back(A);
+      keep.push_back(tau);
+      if (m > 0) jobs[nj++] = gpu::QrJob{A->p, R[k]->p, P.Q[k]->p, tau->p, n, m};
+    }
+  }
+  {
+    double fl = 0.0, by = 0.0;
+    for (int i = 0; i < nj; ++i) {
+      const double n = jobs[i].n, m = jobs[i].m;
+      fl += 2.0 * (2.0 * n * m * m - 2.0 * m * m * m / 3.0);  // factorization + explicit Q
+      by += 8.0 * (2.0 * n * m + m * m);
+    }
+    Prof pr(ctx, PK_QR, by, fl);
+    gpu::householder_qr(ctx->stream, jobs, nj);
+  }
+  // Z = sum_b c_b G_b x_1 R_1[:, b] x_2 R_2[:, b] x_3 R_3[:, b]
+  const long long zsz = (long long)P.q[0] * P.q[1] * P.q[2];
+  P.Z = alloc(ctx, (size_t)std::max<long long>(zsz, 1));
+  gpu::fill(ctx->stream, P.Z->p, zsz, 0.0);
+  for (const auto& b : y->blocks) {
+    if (prod3(b.r) == 0 || zsz == 0) continue;
+    const double* M[3];
+    int ldm[3];
+    for (int k = 0; k < 3; ++k) {
+      M[k] = R[k]->p + (size_t)b.off[k] * P.q[k];
+      ldm[k] = P.q[k];
+    }
+    // first two contractions, then accumulate the third directly into Z
+    int dims[3] = {b.r[0], b.r[1], b.r[2]};
+    const double* cur = b.core->p;
+    BufP hold;
+    for (int k = 0; k < 2; ++k) {
+      const int a = dims[0], bc = dims[1] * dims[2];
+      BufP out = alloc(ctx, (size_t)bc * P.q[k]);
+      gemm(ctx, true, true, bc, P.q[k], a, 1.0, cur, a, M[k], ldm[k], 0.0, out->p, bc);
+      hold = out;
+      cur = out->p;
+      dims[0] = dims[1];
+      dims[1] = dims[2];
+      dims[2] = P.q[k];
+    }
+    const int a = dims[0], bc = dims[1] * dims[2];  // a = r2, bc = q0 q1
+    gemm(ctx, true, true, bc, P.q[2], a, b.c, cur, a, M[2], ldm[2], 1.0, P.Z->p, bc);
+  }
+  return P;
+}
+
+// Steps 3-4: ST-HOSVD of Z with tolerance eps, factors Q_k S_k.
+static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double* disc_rel) {
+  int dims[3] = {P.q[0], P.q[1], P.q[2]};
+  BufP cur = P.Z;
+  BufP S[3];
+  int s_k[3] = {0, 0, 0};
+  double disc_total = 0.0;
+  double* norm2 = ctx->scal->p + 300;
+  double* disc = ctx->scal->p + 301;
+  const long long zsz = (long long)dims[0] * dims[1] * dims[2];
+  bool zero = (zsz == 0);
+  for (int k = 0; k < 3 && !zero; ++k) {
+    const int a = dims[0], bc = dims[1] * dims[2];
+    // Gram of the mode-k unfolding (the current leading mode)
+    BufP G = alloc(ctx, (size_t)a * a);
+    gemm(ctx, false, true, a, a, bc, 1.0, cur->p, a, cur->p, a, 0.0, G->p, a);
+    BufP V = alloc(ctx, (size_t)a * a), w = alloc(ctx, (size_t)a);
+    BufP work;
+    if (((a + 1) & ~1) > 140) work = alloc(ctx, (size_t)(a + 1) * (a + 1));
+    int* sweeps_dev = reinterpret_cast<int*>(ctx->sel->p) + 2100;
+    {
+      Prof pr(ctx, PK_JACOBI, 8.0 * 2.0 * a * (double)a, 0.0);
+      gpu::jacobi_eig(ctx->stream, G->p, a, V->p, w->p, work ? work->p : nullptr, sweeps_dev);
+    }
+    // P = A^T V (bc x a): columns are the mode-k coordinates in the eigenbasis
+    BufP Pm = alloc(ctx, (size_t)bc * a);
+    gemm(ctx, true, false, bc, a, a, 1.0, cur->p, a, V->p, a, 0.0, Pm->p, bc);
+    BufP e = alloc(ctx, (size_t)a);
+    int* sel = reinterpret_cast<int*>(ctx->sel->p);
+    {
+      Prof pr(ctx, PK_SELECT, 8.0 * bc * (double)a, 2.0 * bc * (double)a);
+      gpu::column_energy(ctx->stream, Pm->p, bc, a, e->p);
+      gpu::select_rank(ctx->stream, e->p, a, eps, norm2, k == 0 ? 1 : 0, sel, disc);
+    }
+    int hsel = 0, hsweeps = 0;
+    double hdisc = 0.0;
+    HIPCHK(hipMemcpyAsync(&hsel, sel, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    if (ctx->prof) HIPCHK(hipMemcpyAsync(&hsweeps, sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(&hdisc, disc, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    if (k == 0) HIPCHK(hipMemcpyAsync(&P.norm2, norm2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    if (ctx->prof) {
+      // flops of the parallel Jacobi sweeps: (P-1) rounds of (P/2)^2 two-sided
+      // 2x2 block updates (24 flops) and a*P/2 eigenvector pairs (6 flops)
+      const double Pd = double((a + 1) & ~1);
+      ctx->p_flops[PK_JACOBI] += hsweeps * (Pd - 1.0) * (6.0 * Pd * Pd + 3.0 * a * Pd);
+    }
+    disc_total += hdisc;
+    const int s = hsel;
+    s_k[k] = s;
+    if (s == 0) {
+      zero = true;
+      break;
+    }
+    S[k] = alloc(ctx, (size_t)a * s);
+    BufP next = alloc(ctx, (size_t)bc * s);  // rotated core (b, c, s)
+    {
+      Prof pr(ctx, PK_SELECT, 16.0 * ((double)a * s + (double)bc * s), 0.0);
+      gpu::gather_columns(ctx->stream, V->p, a, sel + 1, s, S[k]->p);
+      gpu::gather_columns(ctx->stream, Pm->p, bc, sel + 1, s, next->p);
+    }
+    cur = next;
+    dims[0] = dims[1];
+    dims[1] = dims[2];
+    dims[2] = s;
+  }
+  if (disc_rel) *disc_rel = (P.norm2 > 0) ? disc_total / P.norm2 : 0.0;
+  int n[3] = {P.n[0], P.n[1], P.n[2]};
+  if (zero) {
+    int r0[3] = {0, 0, 0};
+    return make_plain(ctx, n, r0);
+  }
+  auto* t = new tk_tucker;
+  for (int k = 0; k < 3; ++k) {
+    t->n[k] = n[k];
+    t->m[k] = s_k[k];
+    if (P.ident[k]) {
+      t->U[k] = S[k];  // Q = I: the factor is S_k (n x s)
+    } else {
+      t->U[k] = alloc(ctx, (size_t)n[k] * s_k[k]);
+      gemm(ctx, false, false, n[k], s_k[k], P.q[k], 1.0, P.Q[k]->p, n[k], S[k]->p, P.q[k], 0.0, t->U[k]->p, n[k]);
+    }
+  }
+  Block b;
+  b.core = cur;
+  for (int k = 0; k < 3; ++k) b.r[k] = s_k[k];
+  t->blocks.push_back(b);
+  return t;
+}
+
+static tk_tucker* truncate(tk_ctx* ctx, const tk_tucker* y, double eps, double* disc) {
+  TruncPrep P = truncate_prepare(ctx, y);
+  return truncate_finish(ctx, P, eps, disc);
+}
+
+static double core_norm(tk_ctx* ctx, const tk_tucker* t) {
+  // plain tensor with orthonormal factors: ||t|| = ||core||_F
+  const auto& b = t->blocks[0];
+  if (prod3(b.r) == 0) return 0.0;
+  double* acc = ctx->scal->p;
+  gpu::fill(ctx->stream, acc, 1, 0.0);
+  gpu::dot_accumulate(ctx->stream, b.core->p, b.core->p, prod3(b.r), 1.0, acc);
+  auto h = d2h(ctx, acc, 1);
+  return std::sqrt(std::max(h[0], 0.0)) * std::fabs(b.c);
+}
+
+// ---------------------------------------------------------------------------
+// operator application (eq. tt_product)
+// ---------------------------------------------------------------------------
+
+static tk_tucker* apply_op(tk_ctx* ctx, const tk_op* op, const tk_tucker* x) {
+  for (int k = 0; k < 3; ++k)
+    if (x->n[k] != op->n[k]) throw Error(TK_EINVAL, "operator and tensor sizes differ");
+  auto* t = new tk_tucker;
+  for (int k = 0; k < 3; ++k) {
+    t->n[k] = x->n[k];
+    t->m[k] = op->nmat[k] * x->m[k];
+    t->U[k] = alloc(ctx, (size_t)t->n[k] * t->m[k]);
+    const double nn = x->n[k], mm = x->m[k], R = op->nmat[k], nb = 2 * op->p + 1;
+    Prof pr(ctx, PK_BAND, 8.0 * (nn * mm + R * nb * nn + R * nn * mm), 2.0 * R * nb * nn * mm);
+    gpu::band_apply(ctx->stream, x->n[k], x->m[k], op->nmat[k], op->p, op->band[k]->p, x->U[k]->p,
+                    x->n[k], t->U[k]->p, t->n[k]);
+  }
+  for (const auto& z : op->nz)
+    for (const auto& b : x->blocks) {
+      Block c = b;
+      c.c = b.c * z.c;
+      c.off[0] = z.i1 * x->m[0] + b.off[0];
+      c.off[1] = z.i2 * x->m[1] + b.off[1];
+      c.off[2] = z.i3 * x->m[2] + b.off[2];
+      t->blocks.push_back(c);
+    }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// low-rank FD application (Algorithm 4, steps 5-9)
+// ---------------------------------------------------------------------------
+
+static tk_tucker* apply_prec(tk_ctx* ctx, const tk_prec* P, const tk_tucker* s) {
+  if (s->blocks.size() != 1) throw Error(TK_EINVAL, "fd_precond expects a plain (truncated) Tucker tensor");
+  for (int k = 0; k < 3; ++k)
+    if (s->n[k] != P->dir[k].n) throw Error(TK_EINVAL, "preconditioner and tensor sizes differ");
+  auto* t = new tk_tucker;
+  const Block& sb = s->blocks[0];
+  for (int k = 0; k < 3; ++k) {
+    const int n = s->n[k], r = s->m[k];
+    t->n[k] = n;
+    t->m[k] = P->R * r;
+    t->U[k] = alloc(ctx, (size_t)n * t->m[k]);
+    if (r == 0) continue;
+    BufP Z = alloc(ctx, (size_t)n * r);
+    const auto& d = P->dev[k];
+    const double L = 2.0 * d.N, lg = std::log2(L);
+    {
+      // algorithmic bytes: read S, write Z, boundary map and V2U2 columns
+      Prof pr(ctx, PK_FD_FWD, 8.0 * (2.0 * n * r + (double)n * d.n2),
+              r * (5.0 * L * lg + 2.0 * n * (d.ket + d.n2)));
+      gpu::fd_forward(ctx->stream, d, s->U[k]->p, n, r, Z->p);
+    }
+    {
+      // read Z and the exp table, write R_P r columns
+      Prof pr(ctx, PK_FD_BWD, 8.0 * ((double)n * r + (double)P->R * n + (double)P->R * n * r + (double)n * d.n2),
+              (double)P->R * r * (5.0 * L * lg + 2.0 * n * (d.ke + d.n2) + 3.0 * n));
+      gpu::fd_backward(ctx->stream, d, Z->p, r, t->U[k]->p);
+    }
+  }
+  for (int j = 0; j < P->R; ++j) {
+    Block c = sb;
+    c.c = sb.c * P->omega[j] / P->lam_min;
+    for (int k = 0; k < 3; ++k) c.off[k] = j * s->m[k] + sb.off[k];
+    t->blocks.push_back(c);
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// TPCG (Algorithm 5) with dynamic truncation of the iterate (Algorithm 2)
+// ---------------------------------------------------------------------------
+
+struct Owned {
+  tk_tucker* t = nullptr;
+  Owned() = default;
+  explicit Owned(tk_tucker* x) : t(x) {}
+  Owned(const Owned&) = delete;
+  Owned& operator=(const Owned&) = delete;
+  Owned(Owned&& o) noexcept : t(o.t) { o.t = nullptr; }
+  Owned& operator=(Owned&& o) noexcept {
+    if (this != &o) { delete t; t = o.t; o.t = nullptr; }
+    return *this;
+  }
+  ~Owned() { delete t; }
+  tk_tucker* release() { tk_tucker* x = t; t = nullptr; return x; }
+};
+
+static tk_tucker* scaled_copy(tk_ctx* ctx, const tk_tucker* x, double a) {
+  auto* t = new tk_tucker(*x);  // shares buffers (immutable), scales block coefficients
+  for (auto& b : t->blocks) b.c *= a;
+  return t;
+}
+
+static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_tucker* f_in,
+                      const tk_tpcg_params& prm, tk_tucker** x_out, tk_tpcg_info* info) {
+  tk_tpcg_info inf{};
+  const double tol = prm.tol, beta = prm.beta, alpha = prm.alpha, delta = prm.delta;
+  const double eps_min = prm.eps_min > 0 ? prm.eps_min : 0.1 * tol;
+  const int n[3] = {f_in->n[0], f_in->n[1], f_in->n[2]};
+  const double nf = std::sqrt(std::max(dot(ctx, f_in, f_in), 0.0));
+  if (nf == 0.0) {
+    int r0[3] = {0, 0, 0};
+    *x_out = make_plain(ctx, n, r0);
+    inf.converged = 1;
+    if (info) *info = inf;
+    return TK_OK;
+  }
+  Owned f(scaled_copy(ctx, f_in, 1.0 / nf));  // ||f|| = 1
+  int r0[3] = {0, 0, 0};
+  Owned x(make_plain(ctx, n, r0));
+  Owned r(scaled_copy(ctx, f.t, 1.0));  // r_0 = f (x_0 = 0)
+  double nr = 1.0;
+  if (r.t->blocks.size() != 1) {
+    r = Owned(truncate(ctx, r.t, 0.0, nullptr));
+    nr = core_norm(ctx, r.t);
+  }
+  double eta = beta * tol / nr;
+  Owned pz(apply_prec(ctx, P, r.t));
+  Owned z(truncate(ctx, pz.t, eta, nullptr));
+  pz = Owned();
+  Owned p(scaled_copy(ctx, z.t, 1.0));
+  Owned ap(apply_op(ctx, op, p.t));
+  Owned q(truncate(ctx, ap.t, eta, nullptr));
+  ap = Owned();
+  inf.trel_calls = 2;
+  double xi = dot(ctx, p.t, q.t);
+  double eps = prm.eps0;
+  int k = 0;
+  tk_status st = TK_OK;
+  while (nr > tol && k < prm.maxit) {
+    if (!std::isfinite(xi) || xi <= 0.0) { st = TK_EBREAKDOWN; break; }
+    const double om = dot(ctx, r.t, p.t) / xi;
+    if (!std::isfinite(om)) { st = TK_EBREAKDOWN; break; }
+    // Algorithm 2 on y~ = x_k + om p_k with dy~ = om p_k
+    Owned yt(lin_comb(ctx, 1.0, x.t, om, p.t));
+    TruncPrep prep = truncate_prepare(ctx, yt.t);
+    const double den = om * om * dot(ctx, p.t, p.t);
+    const double base = om * dot(ctx, p.t, x.t);
+    double eps_new = eps;
+    Owned x1;
+    while (true) {
+      x1 = Owned(truncate_finish(ctx, prep, eps_new, nullptr));
+      ++inf.trel_calls;
+      if (den == 0.0) break;
+      const double v = (om * dot(ctx, p.t, x1.t) - base) / den;
+      if (std::fabs(v - 1.0) < delta) break;
+      if (alpha * eps_new > eps_min) eps_new *= alpha;
+      else break;
+    }
+    eps = eps_new;
+    x = std::move(x1);
+    yt = Owned();
+    // r_{k+1} = T^rel(f - A x_{k+1}, eta_k)
+    Owned ax(apply_op(ctx, op, x.t));
+    Owned res(lin_comb(ctx, 1.0, f.t, -1.0, ax.t));
+    ax = Owned();
+    r = Owned(truncate(ctx, res.t, eta, nullptr));
+    res = Owned();
+    ++inf.trel_calls;
+    nr = core_norm(ctx, r.t);
+    ++k;
+    if (prm.verbose)
+      std::fprintf(stderr, "tpcg it %d relres %.3e rank (%d,%d,%d) eps %.2e\n", k, nr, x.t->m[0],
+                   x.t->m[1], x.t->m[2], eps);
+    if (!std::isfinite(nr)) { st = TK_EBREAKDOWN; break; }
+    if (nr <= tol) break;
+    eta = beta * tol / nr;
+    pz = Owned(apply_prec(ctx, P, r.t));
+    z = Owned(truncate(ctx, pz.t, eta, nullptr));
+    pz = Owned();
+    const double bk = -dot(ctx, z.t, q.t) / xi;
+    Owned zp(lin_comb(ctx, 1.0, z.t, bk, p.t));
+    p = Owned(truncate(ctx, zp.t, eta, nullptr));
+    zp = Owned();
+    ap = Owned(apply_op(ctx, op, p.t));
+    q = Owned(truncate(ctx, ap.t, eta, nullptr));
+    ap = Owned();
+    xi = dot(ctx, p.t, q.t);
+    inf.trel_calls += 3;
+  }
+  inf.iters = k;
+  inf.relres = nr;
+  inf.converged = nr <= tol;
+  inf.eps_final = eps;
+  if (st == TK_OK && !inf.converged) st = TK_ENOCONV;
+  // scale back: x * ||f||
+  tk_tucker* xo = x.release();
+  for (auto& b : xo->blocks) b.c *= nf;
+  for (int kk = 0; kk < 3; ++kk) inf.rank[kk] = xo->m[kk];
+  *x_out = xo;
+  if (info) *info = inf;
+  return st;
+}
+
+}  // namespace tk
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+using namespace tk;
+
+template <class F>
+static tk_status guarded(tk_ctx* ctx, F&& f) {
+  try {
+    if (ctx) HIPCHK(hipSetDevice(ctx->device));
+    return f();
+  } catch (const Error& e) {
+    if (ctx) ctx->last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->last_error = "host allocation failed";
+    return TK_ENOMEM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->last_error = e.what();
+    return TK_EDEVICE;
+  }
+}
+
+extern "C" {
+
+tk_status tk_ctx_create(int device, void* hip_stream, tk_ctx** out) {
+  if (!out) return TK_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TK_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return TK_EDEVICE;
+  auto* c = new tk_ctx;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->pool = std::make_unique<Pool>(device);
+  tk_status st = guarded(c, [&]() {
+    c->scal = alloc(c, 512);
+    c->sel = alloc(c, 1100);  // 2200 ints
+    return TK_OK;
+  });
+  if (st != TK_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return TK_OK;
+}
+
+void tk_ctx_destroy(tk_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& r : ctx->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : ctx->evpool) (void)hipEventDestroy(e);
+  ctx->scal.reset();
+  ctx->sel.reset();
+  delete ctx;
+}
+
+const char* tk_last_error(const tk_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
+
+tk_status tk_ctx_sync(tk_ctx* ctx) {
+  if (!ctx) return TK_EINVAL;
+  return guarded(ctx, [&]() { sync(ctx); return TK_OK; });
+}
+
+tk_status tk_ctx_trim(tk_ctx* ctx) {
+  if (!ctx) return TK_EINVAL;
+  return guarded(ctx, [&]() { sync(ctx); ctx->pool->trim(); return TK_OK; });
+}
+
+tk_status tk_assemble_1d(int32_t n_el, int32_t p, int32_t kind, const double weight[4], double* band) {
+  if (n_el < 1 || p < 1 || kind < 0 || kind > 3 || !weight || !band) return TK_EINVAL;
+  if (n_el + p - 2 < 1) return TK_EINVAL;
+  try {
+    assemble_band(n_el, p, kind, weight, band);
+  } catch (...) {
+    return TK_ENOMEM;
+  }
+  return TK_OK;
+}
+
+tk_status tk_load_vector_1d(int32_t n_el, int32_t p, const double weight[4], double* F) {
+  if (n_el < 1 || p < 1 || !weight || !F || n_el + p - 2 < 1) return TK_EINVAL;
+  try {
+    load_vector(n_el, p, weight, F);
+  } catch (...) {
+    return TK_ENOMEM;
+  }
+  return TK_OK;
+}
+
+tk_status tk_fd_direction_host(int32_t n_el, int32_t p, double coef, int32_t* n, int32_t* n1, int32_t* n2,
+                               double* lam, double* g, double* E, double* v2u2) {
+  try {
+    FdDirection d;
+    std::string msg;
+    if (!(coef > 0.0) || !fd_direction_setup(n_el, p, coef, d, msg)) return TK_EINVAL;
+    if (n) *n = d.n;
+    if (n1) *n1 = d.n1;
+    if (n2) *n2 = d.n2;
+    if (lam) std::copy(d.lam.begin(), d.lam.end(), lam);
+    if (g) std::copy(d.g.begin(), d.g.end(), g);
+    if (v2u2) std::copy(d.v2u2.begin(), d.v2u2.end(), v2u2);
+    if (E) {
+      std::fill(E, E + (size_t)d.n * d.n1, 0.0);
+      for (int i = 0; i < d.n; ++i)
+        for (int c = 0; c < d.ke; ++c) {
+          const int j = d.e_idx[(size_t)i * d.ke + c];
+          if (j >= 0) E[i + (size_t)j * d.n] = d.e_val[(size_t)i * d.ke + c];
+        }
+    }
+    return TK_OK;
+  } catch (...) {
+    return TK_ENOMEM;
+  }
+}
+
+tk_status tk_expsum_host(double M, double eps, int32_t* R, double* alpha, double* omega, double* err,
+                         double* err_prev) {
+  try {
+    ExpSum es;
+    std::string msg;
+    if (!expsum_for(M, eps, es, msg)) return TK_ENUMERIC;
+    if (es.R > 64) return TK_ENUMERIC;
+    if (R) *R = es.R;
+    for (int j = 0; j < es.R; ++j) {
+      if (alpha) alpha[j] = es.alpha[j];
+      if (omega) omega[j] = es.omega[j];
+    }
+    if (err) *err = es.err;
+    if (err_prev) *err_prev = es.err_prev;
+    return TK_OK;
+  } catch (...) {
+    return TK_ENOMEM;
+  }
+}
+
+tk_status tk_tucker_create(tk_ctx* ctx, const int64_t n[3], const int64_t r[3], const double* core,
+                           const double* const U[3], int32_t on_device, tk_tucker** out) {
+  if (!ctx || !n || !r || !out) return TK_EINVAL;
+  *out = nullptr;
+  return guarded(ctx, [&]() {
+    int nn[3], rr[3];
+    for (int k = 0; k < 3; ++k) {
+      if (n[k] < 1 || r[k] < 0 || n[k] > (1 << 20) || r[k] > (1 << 16)) throw Error(TK_EINVAL, "bad Tucker shape");
+      nn[k] = int(n[k]);
+      rr[k] = int(r[k]);
+    }
+    const bool empty = prod3(rr) == 0;
+    if (empty) for (int k = 0; k < 3; ++k) rr[k] = 0;
+    if (!empty && (!core || !U || !U[0] || !U[1] || !U[2])) throw Error(TK_EINVAL, "null data pointer");
+    Owned t(make_plain(ctx, nn, rr));
+    if (!empty) {
+      auto cp = [&](double* dst, const double* src, size_t cnt) {
+        if (on_device) d2d(ctx, dst, src, cnt);
+        else h2d(ctx, dst, src, cnt);
+      };
+      cp(t.t->blocks[0].core->p, core, (size_t)prod3(rr));
+      for (int k = 0; k < 3; ++k) cp(t.t->U[k]->p, U[k], (size_t)nn[k] * rr[k]);
+    }
+    *out = t.release();
+    return TK_OK;
+  });
+}
+
+void tk_tucker_free(tk_tucker* t) { delete t; }
+
+tk_status tk_tucker_shape(const tk_tucker* t, int64_t n[3], int64_t m[3], int32_t* nblocks) {
+  if (!t) return TK_EINVAL;
+  for (int k = 0; k < 3; ++k) {
+    if (n) n[k] = t->n[k];
+    if (m) m[k] = t->m[k];
+  }
+  if (nblocks) *nblocks = int32_t(t->blocks.size());
+  return TK_OK;
+}
+
+tk_status tk_tucker_block(const tk_tucker* t, int32_t b, double* coef, int64_t r[3], int64_t off[3]) {
+  if (!t || b < 0 || b >= int32_t(t->blocks.size())) return TK_EINVAL;
+  const auto& bl = t->blocks[b];
+  if (coef) *coef = bl.c;
+  for (int k = 0; k < 3; ++k) {
+    if (r) r[k] = bl.r[k];
+    if (off) off[k] = bl.off[k];
+  }
+  return TK_OK;
+}
+
+tk_status tk_tucker_read(tk_ctx* ctx, const tk_tucker* t, int32_t k, double* U, int32_t b, double* core,
+                         int32_t on_device) {
+  if (!ctx || !t) return TK_EINVAL;
+  return guarded(ctx, [&]() {
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (U) {
+      if (k < 0 || k > 2) throw Error(TK_EINVAL, "mode out of range");
+      const size_t cnt = (size_t)t->n[k] * t->m[k];
+      if (cnt) HIPCHK(hipMemcpyAsync(U, t->U[k]->p, cnt * sizeof(double), kind, ctx->stream));
+    }
+    if (core) {
+      if (b < 0 || b >= int(t->blocks.size())) throw Error(TK_EINVAL, "block out of range");
+      const size_t cnt = (size_t)prod3(t->blocks[b].r);
+      if (cnt) HIPCHK(hipMemcpyAsync(core, t->blocks[b].core->p, cnt * sizeof(double), kind, ctx->stream));
+    }
+    sync(ctx);
+    return TK_OK;
+  });
+}
+
+tk_status tk_tucker_dot(tk_ctx* ctx, const tk_tucker* x, const tk_tucker* y, double* out) {
+  if (!ctx || !x || !y || !out) return TK_EINVAL;
+  return guarded(ctx, [&]() { *out = dot(ctx, x, y); return TK_OK; });
+}
+
+tk_status tk_tucker_axpby(tk_ctx* ctx, double a, const tk_tucker* x, double b, const tk_tucker* y,
+                          tk_tucker** out) {
+  if (!ctx || !x || !y || !out) return TK_EINVAL;
+  *out = nullptr;
+  return guarded(ctx, [&]() { *out = lin_comb(ctx, a, x, b, y); return TK_OK; });
+}
+
+tk_status tk_op_create(tk_ctx* ctx, int32_t p, const int64_t n[3], const int32_t nmat[3],
+                       const double* const bands[3], const tk_core_nz* nz, int64_t nnz, tk_op** out) {
+  if (!ctx || !n || !nmat || !bands || !out || (nnz > 0 && !nz) || nnz < 0 || p < 0) return TK_EINVAL;
+  *out = nullptr;
+  return guarded(ctx, [&]() {
+    std::unique_ptr<tk_op> op(new tk_op);
+    op->p = p;
+    for (int k = 0; k < 3; ++k) {
+      if (n[k] < 1 || nmat[k] < 1 || !bands[k]) throw Error(TK_EINVAL, "bad operator mode");
+      op->n[k] = int(n[k]);
+      op->nmat[k] = nmat[k];
+      const size_t cnt = (size_t)nmat[k] * (2 * p + 1) * n[k];
+      op->band[k] = alloc(ctx, cnt);
+      h2d(ctx, op->band[k]->p, bands[k], cnt);
+    }
+    for (int64_t i = 0; i < nnz; ++i) {
+      if (nz[i].i1 < 0 || nz[i].i1 >= nmat[0] || nz[i].i2 < 0 || nz[i].i2 >= nmat[1] || nz[i].i3 < 0 ||
+          nz[i].i3 >= nmat[2])
+        throw Error(TK_EINVAL, "core nonzero index out of range");
+      op->nz.push_back(nz[i]);
+    }
+    *out = op.release();
+    return TK_OK;
+  });
+}
+
+void tk_op_free(tk_op* op) { delete op; }
+
+tk_status tucker_apply_op(tk_ctx* ctx, const tk_op* op, const tk_tucker* x, tk_tucker** y) {
+  if (!ctx || !op || !x || !y) return TK_EINVAL;
+  *y = nullptr;
+  return guarded(ctx, [&]() { *y = apply_op(ctx, op, x); return TK_OK; });
+}
+
+tk_status fd_setup(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec, const double coef[3],
+                   tk_prec** out, int32_t* R_P) {
+  if (!ctx || !n_el || !out || !(eps_prec > 0.0)) return TK_EINVAL;
+  *out = nullptr;
+  return guarded(ctx, [&]() {
+    std::unique_ptr<tk_prec> P(new tk_prec);
+    std::string msg;
+    P->lam_min = 0.0;
+    P->lam_max = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double c = coef ? coef[k] : 1.0;
+      if (!(c > 0.0)) throw Error(TK_EINVAL, "fd_setup: direction coefficients must be positive");
+      if (!fd_direction_setup(n_el[k], p, c, P->dir[k], msg)) throw Error(TK_EINVAL, msg);
+      const auto& l = P->dir[k].lam;
+      P->lam_min += *std::min_element(l.begin(), l.end());
+      P->lam_max += *std::max_element(l.begin(), l.end());
+    }
+    const double MP = P->lam_max / P->lam_min;
+    ExpSum es;
+    if (!expsum_for(MP, eps_prec, es, msg)) throw Error(TK_ENUMERIC, msg);
+    P->R = es.R;
+    P->alpha = es.alpha;
+    P->omega = es.omega;
+    P->err = es.err;
+    P->err_prev = es.err_prev;
+    const double pi = 3.14159265358979323846;
+    for (int k = 0; k < 3; ++k) {
+      const auto& d = P->dir[k];
+      std::vector<double> expD((size_t)P->R * d.n);
+      for (int j = 0; j < P->R; ++j)
+        for (int m = 0; m < d.n; ++m) expD[(size_t)j * d.n + m] = std::exp(-P->alpha[j] * d.lam[m] / P->lam_min);
+      std::vector<double> tw(2 * (size_t)d.N);
+      for (int t = 0; t < d.N; ++t) {
+        tw[2 * t] = std::cos(2.0 * pi * t / (2.0 * d.N));
+        tw[2 * t + 1] = -std::sin(2.0 * pi * t / (2.0 * d.N));
+      }
+      auto up = [&](const std::vector<double>& v) {
+        BufP b = alloc(ctx, v.size());
+        h2d(ctx, b->p, v.data(), v.size());
+        return b;
+      };
+      auto up_int = [&](const std::vector<int>& v) {
+        BufP b = alloc(ctx, (v.size() + 1) / 2);
+        if (!v.empty()) {
+          HIPCHK(hipMemcpyAsync(b->p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+          sync(ctx);
+        }
+        return b;
+      };
+      P->g[k] = up(d.g);
+      P->e_val[k] = up(d.e_val);
+      P->et_val[k] = up(d.et_val);
+      P->v2u2[k] = up(d.v2u2);
+      P->expD[k] = up(expD);
+      P->tw[k] = up(tw);
+      P->e_idx[k] = up_int(d.e_idx);
+      P->et_idx[k] = up_int(d.et_idx);
+      gpu::FdDev& dv = P->dev[k];
+      dv.n = d.n;
+      dv.n1 = d.n1;
+      dv.n2 = d.n2;
+      dv.N = d.N;
+      dv.odd = d.odd ? 1 : 0;
+      dv.ke = d.ke;
+      dv.ket = d.ket;
+      dv.R = P->R;
+      dv.g = P->g[k]->p;
+      dv.e_idx = reinterpret_cast<const int*>(P->e_idx[k]->p);
+      dv.e_val = P->e_val[k]->p;
+      dv.et_idx = reinterpret_cast<const int*>(P->et_idx[k]->p);
+      dv.et_val = P->et_val[k]->p;
+      dv.v2u2 = P->v2u2[k]->p;
+      dv.expD = P->expD[k]->p;
+      dv.tw = reinterpret_cast<const double2*>(P->tw[k]->p);
+    }
+    if (R_P) *R_P = P->R;
+    *out = P.release();
+    return TK_OK;
+  });
+}
+
+void tk_prec_free(tk_prec* P) { delete P; }
+
+tk_status tk_prec_info(const tk_prec* P, int32_t* R_P, double* lam_min, double* lam_max, double* err,
+                       double* alpha, double* omega) {
+  if (!P) return TK_EINVAL;
+  if (R_P) *R_P = P->R;
+  if (lam_min) *lam_min = P->lam_min;
+  if (lam_max) *lam_max = P->lam_max;
+  if (err) *err = P->err;
+  for (int j = 0; j < P->R; ++j) {
+    if (alpha) alpha[j] = P->alpha[j];
+    if (omega) omega[j] = P->omega[j];
+  }
+  return TK_OK;
+}
+
+tk_status tk_prec_direction(const tk_prec* P, int32_t k, int32_t* n, int32_t* n1, int32_t* n2, double* lam,
+                            double* g, double* E, double* v2u2) {
+  if (!P || k < 0 || k > 2) return TK_EINVAL;
+  const auto& d = P->dir[k];
+  if (n) *n = d.n;
+  if (n1) *n1 = d.n1;
+  if (n2) *n2 = d.n2;
+  if (lam) std::copy(d.lam.begin(), d.lam.end(), lam);
+  if (g) std::copy(d.g.begin(), d.g.end(), g);
+  if (v2u2) std::copy(d.v2u2.begin(), d.v2u2.end(), v2u2);
+  if (E) {
+    std::fill(E, E + (size_t)d.n * d.n1, 0.0);
+    for (int i = 0; i < d.n; ++i)
+      for (int c = 0; c < d.ke; ++c) {
+        const int j = d.e_idx[(size_t)i * d.ke + c];
+        if (j >= 0) E[i + (size_t)j * d.n] = d.e_val[(size_t)i * d.ke + c];
+      }
+  }
+  return TK_OK;
+}
+
+tk_status fd_precond(tk_ctx* ctx, const tk_prec* P, const tk_tucker* s, tk_tucker** v) {
+  if (!ctx || !P || !s || !v) return TK_EINVAL;
+  *v = nullptr;
+  return guarded(ctx, [&]() { *v = apply_prec(ctx, P, s); return TK_OK; });
+}
+
+tk_status tucker_truncate(tk_ctx* ctx, const tk_tucker* y, double eps, tk_tucker** out, double* discarded) {
+  if (!ctx || !y || !out || !(eps >= 0.0)) return TK_EINVAL;
+  *out = nullptr;
+  return guarded(ctx, [&]() { *out = truncate(ctx, y, eps, discarded); return TK_OK; });
+}
+
+tk_status tk_prof_enable(tk_ctx* ctx, int32_t on) {
+  if (!ctx) return TK_EINVAL;
+  return guarded(ctx, [&]() {
+    prof_flush(ctx);
+    ctx->prof = on != 0;
+    return TK_OK;
+  });
+}
+
+tk_status tk_prof_reset(tk_ctx* ctx) {
+  if (!ctx) return TK_EINVAL;
+  return guarded(ctx, [&]() {
+    prof_flush(ctx);
+    for (int k = 0; k < PK_N; ++k) ctx->p_ms[k] = ctx->p_bytes[k] = ctx->p_flops[k] = 0.0, ctx->p_n[k] = 0;
+    return TK_OK;
+  });
+}
+
+tk_status tk_prof_read(tk_ctx* ctx, int32_t kind, int64_t* launches, double* ms, double* bytes, double* flops) {
+  if (!ctx || kind < 0 || kind >= PK_N) return TK_EINVAL;
+  return guarded(ctx, [&]() {
+    prof_flush(ctx);
+    if (launches) *launches = ctx->p_n[kind];
+    if (ms) *ms = ctx->p_ms[kind];
+    if (bytes) *bytes = ctx->p_bytes[kind];
+    if (flops) *flops = ctx->p_flops[kind];
+    return TK_OK;
+  });
+}
+
+void tk_tpcg_defaults(tk_tpcg_params* p) {
+  if (!p) return;
+  p->tol = 1e-6;
+  p->beta = 0.1;
+  p->eps0 = 0.1;
+  p->alpha = 0.5;
+  p->eps_min = 0.0;
+  p->delta = 1e-3;
+  p->maxit = 1000;
+  p->verbose = 0;
+}
+
+tk_status tpcg_solve(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_tucker* f,
+                     const tk_tpcg_params* params, tk_tucker** x, tk_tpcg_info* info) {
+  if (!ctx || !op || !P || !f || !x) return TK_EINVAL;
+  *x = nullptr;
+  tk_tpcg_params prm;
+  if (params) prm = *params;
+  else tk_tpcg_defaults(&prm);
+  if (!(prm.tol > 0) || !(prm.beta > 0) || !(prm.eps0 > 0) || !(prm.alpha > 0 && prm.alpha < 1) ||
+      !(prm.delta > 0) || prm.maxit < 0) {
+    ctx->last_error = "tpcg_solve: invalid parameters";
+    return TK_EINVAL;
+  }
+  return guarded(ctx, [&]() { return tpcg(ctx, op, P, f, prm, x, info); });
+}
+
+}  // extern "C"

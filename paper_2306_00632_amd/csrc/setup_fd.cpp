@@ -1,0 +1,404 @@
+// Host setup of the low-rank Fast Diagonalization transform of one direction
+// (Sec. 4.2 Algorithm 4, Appendix B, Dirichlet at both ends).
+//
+// Appendix B approximates the generalized eigenvectors of (K, M) by
+//   U~ = [ V1 U1 | V2 U2 ],  Lambda~ = diag((j pi)^2, Lambda2),
+// where V1 U1 w is the spline of V_h1 interpolating sum_j w_j sqrt(2) sin(j pi x)
+// at the interpolation points (breakpoints for odd p, span midpoints for
+// even p), V_h1 = {phi : phi^(2k)(0) = phi^(2k)(1) = 0, 2k <= p-1}, and V_h2 is
+// the M-orthogonal complement of V_h1 with its exact small eigenproblem.
+//
+// This library applies V1 U1 without the collocation solve.  The functions
+// of V_h1 are exactly the restrictions to [0,1] of odd, 2-periodic splines on
+// the uniform knots (odd reflection keeps C^{p-1} iff the even derivatives
+// vanish at the reflection point).  For such splines interpolation at the
+// breakpoints/midpoints is diagonal in the sine basis: the interpolant of
+// sin(j pi x) is (1/sigma(j pi/N)) sum_k sin(j pi xi_k) B_k(x), with B_k the
+// cardinal B-spline translates, xi_k their centres and sigma the symbol
+//   sigma(theta) = sum_u N_p(u) cos(theta (u - (p+1)/2))
+// over the points u of the interpolation grid inside the support of N_p.  So
+//   V1 U1 = E * DST * diag(g),   g_j = sqrt(2) / sigma(j pi / N),
+// where DST evaluates the sines at the translate centres (DST-I for odd p,
+// DST-III for even p) and the sparse matrix E maps translate coefficients
+// (folded by odd symmetry onto the N-1 resp. N basic centres) to the
+// Dirichlet B-spline basis: identity in the interior, small dense blocks for
+// the translates that cross 0 or 1 (obtained by exact least squares on
+// their support).  (V1 U1)^T = diag(g) DST^T E^T.
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "tk_internal.h"
+
+namespace tk {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Cardinal B-spline of degree d on [0, d+1] (uniform Cox-de Boor recursion).
+double cardinal(int d, double u) {
+  if (d == 0) return (u >= 0.0 && u < 1.0) ? 1.0 : 0.0;
+  return (u * cardinal(d - 1, u) + (d + 1 - u) * cardinal(d - 1, u - 1.0)) / d;
+}
+
+// Dense least squares min ||A x - y|| by Householder QR (A is rows x cols,
+// row-major); returns the residual norm.
+double lstsq(std::vector<double> A, std::vector<double> y, int rows, int cols,
+             std::vector<double>& x) {
+  for (int c = 0; c < cols; ++c) {
+    double nrm = 0.0;
+    for (int i = c; i < rows; ++i) nrm += A[i * cols + c] * A[i * cols + c];
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) continue;
+    const double alpha = (A[c * cols + c] > 0) ? -nrm : nrm;
+    std::vector<double> v(rows - c);
+    for (int i = c; i < rows; ++i) v[i - c] = A[i * cols + c];
+    v[0] -= alpha;
+    double vv = 0.0;
+    for (double t : v) vv += t * t;
+    if (vv == 0.0) continue;
+    for (int k = c; k < cols; ++k) {
+      double s = 0.0;
+      for (int i = c; i < rows; ++i) s += v[i - c] * A[i * cols + k];
+      s = 2.0 * s / vv;
+      for (int i = c; i < rows; ++i) A[i * cols + k] -= s * v[i - c];
+    }
+    double s = 0.0;
+    for (int i = c; i < rows; ++i) s += v[i - c] * y[i];
+    s = 2.0 * s / vv;
+    for (int i = c; i < rows; ++i) y[i] -= s * v[i - c];
+  }
+  x.assign(cols, 0.0);
+  for (int c = cols - 1; c >= 0; --c) {
+    double s = y[c];
+    for (int k = c + 1; k < cols; ++k) s -= A[c * cols + k] * x[k];
+    x[c] = (A[c * cols + c] != 0.0) ? s / A[c * cols + c] : 0.0;
+  }
+  double r = 0.0;
+  for (int i = cols; i < rows; ++i) r += y[i] * y[i];
+  return std::sqrt(r);
+}
+
+// Banded SPD Cholesky: A given in DIA form (2p+1) x n; returns lower factor
+// L[(i)*(p+1) + (i-j)] for j in [i-p, i].
+bool band_cholesky(const std::vector<double>& band, int n, int p, std::vector<double>& L) {
+  L.assign(size_t(n) * (p + 1), 0.0);
+  auto Aij = [&](int i, int j) { return band[size_t(j - i + p) * n + i]; };
+  for (int i = 0; i < n; ++i) {
+    for (int j = std::max(0, i - p); j <= i; ++j) {
+      double s = Aij(i, j);
+      for (int k = std::max(0, i - p); k < j; ++k)
+        s -= L[size_t(i) * (p + 1) + (i - k)] * L[size_t(j) * (p + 1) + (j - k)];
+      if (i == j) {
+        if (s <= 0.0) return false;
+        L[size_t(i) * (p + 1)] = std::sqrt(s);
+      } else {
+        L[size_t(i) * (p + 1) + (i - j)] = s / L[size_t(j) * (p + 1)];
+      }
+    }
+  }
+  return true;
+}
+
+void band_cholesky_solve(const std::vector<double>& L, int n, int p, std::vector<double>& x) {
+  for (int i = 0; i < n; ++i) {
+    double s = x[i];
+    for (int k = std::max(0, i - p); k < i; ++k) s -= L[size_t(i) * (p + 1) + (i - k)] * x[k];
+    x[i] = s / L[size_t(i) * (p + 1)];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = x[i];
+    for (int k = i + 1; k <= std::min(n - 1, i + p); ++k) s -= L[size_t(k) * (p + 1) + (k - i)] * x[k];
+    x[i] = s / L[size_t(i) * (p + 1)];
+  }
+}
+
+void band_matvec(const std::vector<double>& band, int n, int p, const double* x, double* y) {
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int o = -p; o <= p; ++o) {
+      const int j = i + o;
+      if (j >= 0 && j < n) s += band[size_t(o + p) * n + i] * x[j];
+    }
+    y[i] = s;
+  }
+}
+
+// Cyclic Jacobi for a small symmetric matrix (row-major, in place); V gets
+// the eigenvectors as columns.
+void small_jacobi(std::vector<double>& A, int n, std::vector<double>& V) {
+  V.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += A[i * n + j] * A[i * n + j];
+        if (i != j) off += A[i * n + j] * A[i * n + j];
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (apq == 0.0) continue;
+        const double tau = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - s * vkq;
+          V[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+}
+
+}  // namespace
+
+bool fd_direction_setup(int n_el, int p, double coef, FdDirection& d, std::string& msg) {
+  if (p < 1 || n_el <= p) {
+    msg = "fd_setup: need p >= 1 and n_el > p";
+    return false;
+  }
+  if ((n_el & (n_el - 1)) != 0 || n_el < 4 || n_el > 1024) {
+    msg = "fd_setup: n_el must be a power of two in [4, 1024] (radix-2 FFT length 2*n_el)";
+    return false;
+  }
+  const int N = n_el;
+  d.n_el = n_el;
+  d.p = p;
+  d.N = N;
+  d.n = n_el + p - 2;
+  d.odd = (p % 2) == 1;
+  d.n1 = d.odd ? N - 1 : N;
+  d.n2 = d.odd ? p - 1 : p - 2;
+  const int n = d.n, n1 = d.n1, n2 = d.n2;
+  const auto knots = open_knots(n_el, p);
+  const int nfull = n_el + p;
+
+  // symbol sigma(theta) on the interpolation grid and g_j = sqrt(2)/sigma_j
+  std::vector<double> uu, nu;
+  for (int i = 0; i <= 2 * (p + 1); ++i) {
+    const double u = d.odd ? double(i) : i + 0.5;
+    if (u > 0.0 && u < p + 1.0) {
+      uu.push_back(u);
+      nu.push_back(cardinal(p, u));
+    }
+  }
+  d.g.resize(n1);
+  for (int j = 1; j <= n1; ++j) {
+    const double th = kPi * j / N;
+    double s = 0.0;
+    for (size_t k = 0; k < uu.size(); ++k) s += nu[k] * std::cos(th * (uu[k] - 0.5 * (p + 1)));
+    if (!(std::fabs(s) > 1e-12)) {
+      msg = "fd_setup: vanishing interpolation symbol";
+      return false;
+    }
+    d.g[j - 1] = std::sqrt(2.0) / s;
+  }
+
+  // E: translates k = -p .. N-1 (B_k supported on [k/N, (k+p+1)/N])
+  std::vector<double> E(size_t(n) * n1, 0.0), dropped(2 * size_t(n1), 0.0);
+  std::vector<double> vals(p + 1);
+  const int q = d.odd ? (p - 1) / 2 : p / 2;
+  for (int k = -p; k <= N - 1; ++k) {
+    // fold the translate's centre index onto a basic centre, with sign
+    const int m = d.odd ? k + q + 1 : k + q;
+    int base = -1;
+    double sgn = 1.0;
+    if (d.odd) {
+      int mm = m;
+      if (mm < 0) { mm = -mm; sgn = -1.0; }
+      if (mm > N) { mm = 2 * N - mm; sgn = -sgn; }
+      if (mm == 0 || mm == N) continue;  // the sine vanishes there
+      base = mm - 1;
+    } else {
+      int mm = m;
+      if (mm < 0) { mm = -mm - 1; sgn = -1.0; }
+      if (mm >= N) { mm = 2 * N - 1 - mm; sgn = -sgn; }
+      base = mm;
+    }
+    // open-basis coefficients of B_k restricted to [0, 1]
+    std::vector<std::pair<int, double>> coeffs;
+    if (k >= 0 && k <= N - p - 1) {
+      coeffs.push_back({k + p, 1.0});
+    } else {
+      const double a = std::max(0.0, double(k) / N), b = std::min(1.0, double(k + p + 1) / N);
+      std::vector<int> cand;
+      for (int l = 0; l < nfull; ++l)
+        if (knots[l] < b && knots[l + p + 1] > a) cand.push_back(l);
+      const int S = 8 * (p + 1);
+      std::vector<double> A(size_t(S) * cand.size(), 0.0), y(S);
+      for (int s = 0; s < S; ++s) {
+        const double x = a + (b - a) * (s + 0.5) / S;
+        const int span = find_span(knots, p, x);
+        span_basis(knots, p, span, x, 0, vals.data());
+        for (size_t c = 0; c < cand.size(); ++c) {
+          const int loc = cand[c] - (span - p);
+          A[s * cand.size() + c] = (loc >= 0 && loc <= p) ? vals[loc] : 0.0;
+        }
+        y[s] = cardinal(p, x * N - k);
+      }
+      std::vector<double> xs;
+      const double res = lstsq(A, y, S, int(cand.size()), xs);
+      if (res > 1e-10) {
+        msg = "fd_setup: boundary translate not representable";
+        return false;
+      }
+      for (size_t c = 0; c < cand.size(); ++c)
+        if (std::fabs(xs[c]) > 1e-13) coeffs.push_back({cand[c], xs[c]});
+    }
+    for (auto& lc : coeffs) {
+      const int l = lc.first;
+      if (l == 0) dropped[base] += sgn * lc.second;
+      else if (l == nfull - 1) dropped[n1 + base] += sgn * lc.second;
+      else E[size_t(l - 1) * n1 + base] += sgn * lc.second;
+    }
+  }
+  for (double v : dropped)
+    if (std::fabs(v) > 1e-9) {
+      msg = "fd_setup: odd extension does not vanish at the boundary";
+      return false;
+    }
+  // ELL forms of E and E^T
+  int ke = 1, ket = 1;
+  for (int i = 0; i < n; ++i) {
+    int c = 0;
+    for (int j = 0; j < n1; ++j) c += (E[size_t(i) * n1 + j] != 0.0);
+    ke = std::max(ke, c);
+  }
+  for (int j = 0; j < n1; ++j) {
+    int c = 0;
+    for (int i = 0; i < n; ++i) c += (E[size_t(i) * n1 + j] != 0.0);
+    ket = std::max(ket, c);
+  }
+  d.ke = ke;
+  d.ket = ket;
+  d.e_idx.assign(size_t(n) * ke, -1);
+  d.e_val.assign(size_t(n) * ke, 0.0);
+  d.et_idx.assign(size_t(n1) * ket, -1);
+  d.et_val.assign(size_t(n1) * ket, 0.0);
+  for (int i = 0; i < n; ++i) {
+    int c = 0;
+    for (int j = 0; j < n1; ++j)
+      if (E[size_t(i) * n1 + j] != 0.0) {
+        d.e_idx[size_t(i) * ke + c] = j;
+        d.e_val[size_t(i) * ke + c] = E[size_t(i) * n1 + j];
+        ++c;
+      }
+  }
+  for (int j = 0; j < n1; ++j) {
+    int c = 0;
+    for (int i = 0; i < n; ++i)
+      if (E[size_t(i) * n1 + j] != 0.0) {
+        d.et_idx[size_t(j) * ket + c] = i;
+        d.et_val[size_t(j) * ket + c] = E[size_t(i) * n1 + j];
+        ++c;
+      }
+  }
+
+  // eigenvalue approximations on V_h1
+  d.lam.assign(n, 0.0);
+  for (int j = 1; j <= n1; ++j) d.lam[j - 1] = coef * (kPi * j) * (kPi * j);
+
+  // V_h2 = M^{-1} D^T with the even-derivative constraints D, and its pencil
+  d.v2u2.assign(size_t(n) * n2, 0.0);
+  if (n2 > 0) {
+    const double unit[4] = {1.0, 0.0, 0.0, 0.0};
+    std::vector<double> Mb(size_t(2 * p + 1) * n), Kb(size_t(2 * p + 1) * n), L;
+    assemble_band(n_el, p, 0, unit, Mb.data());
+    assemble_band(n_el, p, 1, unit, Kb.data());
+    if (!band_cholesky(Mb, n, p, L)) {
+      msg = "fd_setup: mass matrix not positive definite";
+      return false;
+    }
+    std::vector<double> V2(size_t(n) * n2);  // column-major n x n2
+    int row = 0;
+    for (int end = 0; end < 2; ++end)
+      for (int k = 1; 2 * k <= p - 1; ++k) {
+        std::vector<double> col(n);
+        dirichlet_basis_at(n_el, p, end ? 1.0 : 0.0, 2 * k, col.data());
+        band_cholesky_solve(L, n, p, col);
+        std::copy(col.begin(), col.end(), V2.begin() + size_t(row) * n);
+        ++row;
+      }
+    // small pencil (V2^T K V2, V2^T M V2)
+    std::vector<double> K2(n2 * n2), M2(n2 * n2), tmp(n);
+    for (int b = 0; b < n2; ++b) {
+      band_matvec(Kb, n, p, &V2[size_t(b) * n], tmp.data());
+      for (int a = 0; a < n2; ++a) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += V2[size_t(a) * n + i] * tmp[i];
+        K2[a * n2 + b] = s;
+      }
+      band_matvec(Mb, n, p, &V2[size_t(b) * n], tmp.data());
+      for (int a = 0; a < n2; ++a) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += V2[size_t(a) * n + i] * tmp[i];
+        M2[a * n2 + b] = s;
+      }
+    }
+    // M2 = C C^T (dense Cholesky), then eig of C^{-1} K2 C^{-T}
+    std::vector<double> C(n2 * n2, 0.0);
+    for (int i = 0; i < n2; ++i)
+      for (int j = 0; j <= i; ++j) {
+        double s = M2[i * n2 + j];
+        for (int k = 0; k < j; ++k) s -= C[i * n2 + k] * C[j * n2 + k];
+        if (i == j) {
+          if (s <= 0) { msg = "fd_setup: V_h2 mass not SPD"; return false; }
+          C[i * n2 + i] = std::sqrt(s);
+        } else {
+          C[i * n2 + j] = s / C[j * n2 + j];
+        }
+      }
+    auto lower_solve = [&](std::vector<double>& X) {  // X <- C^{-1} X (n2 x n2 row-major)
+      for (int c = 0; c < n2; ++c)
+        for (int i = 0; i < n2; ++i) {
+          double s = X[i * n2 + c];
+          for (int k = 0; k < i; ++k) s -= C[i * n2 + k] * X[k * n2 + c];
+          X[i * n2 + c] = s / C[i * n2 + i];
+        }
+    };
+    std::vector<double> T = K2;
+    lower_solve(T);  // C^{-1} K2
+    std::vector<double> Tt(n2 * n2);
+    for (int i = 0; i < n2; ++i)
+      for (int j = 0; j < n2; ++j) Tt[i * n2 + j] = T[j * n2 + i];
+    lower_solve(Tt);  // C^{-1} (C^{-1} K2)^T = C^{-1} K2 C^{-T}
+    std::vector<double> Q;
+    small_jacobi(Tt, n2, Q);
+    std::vector<int> ord(n2);
+    for (int i = 0; i < n2; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return Tt[a * n2 + a] < Tt[b * n2 + b]; });
+    // U2 = C^{-T} Q  (upper solve with C^T)
+    std::vector<double> U2(n2 * n2);
+    for (int c = 0; c < n2; ++c)
+      for (int i = n2 - 1; i >= 0; --i) {
+        double s = Q[i * n2 + ord[c]];
+        for (int k = i + 1; k < n2; ++k) s -= C[k * n2 + i] * U2[k * n2 + c];
+        U2[i * n2 + c] = s / C[i * n2 + i];
+      }
+    for (int c = 0; c < n2; ++c) {
+      d.lam[n1 + c] = coef * Tt[ord[c] * n2 + ord[c]];
+      for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int a = 0; a < n2; ++a) s += V2[size_t(a) * n + i] * U2[a * n2 + c];
+        d.v2u2[size_t(c) * n + i] = s;
+      }
+    }
+  }
+  return true;
+}
+
+}  // namespace tk

@@ -1,0 +1,208 @@
+"""GPU parity: every hot-path call of the C ABI (through the ctypes binding)
+against the FP64 oracle on the same seeded inputs.
+
+Tolerances (FP64 throughout the GPU path):
+* operator application and dots: elementwise relative 1e-12 (banded sums of
+  at most 2p+1 products; GEMM reassociation only);
+* truncation: same ranks as the oracle's SVD-based ST-HOSVD, represented
+  tensors within 1e-10 relative (both are the sequentially truncated HOSVD of
+  the same core; the GPU takes singular directions from a Jacobi-diagonalised
+  Gram matrix and measures the discarded energy directly);
+* preconditioner: 1e-9 relative (the exponential-sum parameters of the
+  library's and the oracle's independent Remez solvers agree to ~1e-11);
+* TPCG: relative solution error against the full-tensor reference
+  (exact-FD PCG to 1e-12) below the bound stated per test.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fd as ofd
+from oracle import problem as oprob
+from oracle import tucker as T
+from oracle import fullpcg, tpcg as otpcg
+
+from gpu_helpers import context, rel, say, to_oracle, to_oracle_plain
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return context()
+
+
+def lib_modules():
+    from paper_2306_00632_amd import problem, tk
+    return tk, problem
+
+
+def rnd(n, r, seed):
+    core, U = W.random_tucker(n, r, seed)
+    return T.Tucker(core, U)
+
+
+def upload(ctx, x: T.Tucker):
+    tk, _ = lib_modules()
+    return tk.Tucker.from_host(ctx, x.core, x.U)
+
+
+# --- operator application (eq. tt_product) -------------------------------------
+
+@pytest.mark.parametrize("n_el,p,R,r", [(12, 3, 4, (3, 4, 2)), (128, 3, 9, (5, 7, 6)), (16, 2, 3, (1, 1, 1))])
+def test_apply_op(ctx, n_el, p, R, r):
+    tk, prob = lib_modules()
+    say(f"apply_op n_el={n_el} p={p} R={R} r={r}")
+    w = W.weighted_cp(n_el, p, R, 2, 11, 12) if R != 3 else W.laplace_cube(n_el, p)
+    x = rnd(w.n, r, 5)
+    op_g = prob.operator(ctx, w)
+    y = tk.tucker_apply_op(ctx, op_g, upload(ctx, x))
+    ref = T.apply_op(oprob.operator(w), x)
+    got = to_oracle(y)
+    assert got.m == ref.m
+    for k in range(3):
+        np.testing.assert_allclose(got.U[k], ref.U[k], rtol=1e-12, atol=1e-12 * np.abs(ref.U[k]).max())
+    assert [(c, o) for c, _, o in got.blocks] == [(c, o) for c, _, o in ref.blocks]
+    if n_el <= 16:
+        assert rel(got.full(), ref.full()) < 1e-12
+
+
+# --- scalar products ---------------------------------------------------------------
+
+def test_dot_plain_and_lazy(ctx):
+    tk, _ = lib_modules()
+    say("dot")
+    n = (20, 17, 23)
+    x = rnd(n, (3, 5, 4), 1)
+    y = rnd(n, (6, 2, 3), 2)
+    xg, yg = upload(ctx, x), upload(ctx, y)
+    assert abs(tk.dot(ctx, xg, yg) - T.dot(x, y)) <= 1e-12 * abs(T.dot(x, y))
+    s = tk.axpby(ctx, 2.0, xg, -0.5, yg)
+    ref = T.tsum([(2.0, x), (-0.5, y)])
+    assert abs(tk.dot(ctx, s, xg) - T.dot(ref, x)) <= 1e-12 * T.norm(ref) * T.norm(x)
+    assert abs(tk.dot(ctx, s, s) - T.dot(ref, ref)) <= 1e-12 * T.dot(ref, ref)
+
+
+# --- truncation (Algorithm 1) ----------------------------------------------------------
+
+def _check_trunc(ctx, ysum_oracle, yg, eps):
+    tk, _ = lib_modules()
+    tg, disc = tk.tucker_truncate(ctx, yg, eps)
+    got = to_oracle_plain(tg)
+    ref = T.trel(ysum_oracle, eps)
+    say(f"   eps={eps:g} ranks gpu={got.ranks} oracle={ref.ranks}")
+    assert got.ranks == ref.ranks
+    ny = T.norm(ysum_oracle)
+    if ny > 0:
+        assert T.rel_diff(got, ref) < 1e-10 or T.norm(ref) == 0
+        # relative error bound of eq. (rel_estimate), measured without cancellation
+        assert T.rel_diff(got, ysum_oracle) <= eps * (1 + 1e-8) + 1e-13
+    for U in got.U:
+        np.testing.assert_allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
+
+
+@pytest.mark.parametrize("eps", [1e-1, 1e-4, 1e-8])
+def test_truncate_tall_factors(ctx, eps):
+    """m_k < n_k: Householder QR path."""
+    say(f"truncate tall eps={eps}")
+    n = (40, 37, 45)
+    a, b = rnd(n, (4, 5, 3), 21), rnd(n, (3, 3, 6), 22)
+    yo = T.tsum([(1.0, a), (1e-3, b), (0.5, a)])
+    yg = upload(ctx, a)
+    tk, _ = lib_modules()
+    yg = tk.axpby(ctx, 1.0, yg, 1e-3, upload(ctx, b))
+    yg = tk.axpby(ctx, 1.0, yg, 0.5, upload(ctx, a))
+    _check_trunc(ctx, yo, yg, eps)
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-6])
+def test_truncate_wide_factors(ctx, eps):
+    """m_k >= n_k on some modes (Q = I path), n = 129 spans several tiles."""
+    say(f"truncate wide eps={eps}")
+    tk, _ = lib_modules()
+    n = (129, 24, 129)
+    parts = [rnd(n, (30, 6, 40), 31 + i) for i in range(5)]
+    yo = T.tsum([(1.0 / (i + 1) ** 2, x) for i, x in enumerate(parts)])
+    yg = upload(ctx, parts[0])
+    for i, x in enumerate(parts[1:], start=1):
+        yg = tk.axpby(ctx, 1.0, yg, 1.0 / (i + 1) ** 2, upload(ctx, x))
+    _check_trunc(ctx, yo, yg, eps)
+
+
+def test_truncate_rank_deficient_and_zero(ctx):
+    tk, _ = lib_modules()
+    say("truncate deficient/zero")
+    n = (15, 16, 17)
+    a = rnd(n, (3, 3, 3), 41)
+    yo = T.tsum([(1.0, a), (-1.0, a), (1.0, a)])     # repeated columns, represented rank 3
+    ag = upload(ctx, a)
+    yg = tk.axpby(ctx, 1.0, tk.axpby(ctx, 1.0, ag, -1.0, ag), 1.0, ag)
+    _check_trunc(ctx, yo, yg, 1e-10)
+    # a - a: the QR of [A, A] leaves rounding-level residue whose relative
+    # truncation keeps that residue; only its size is meaningful
+    zg = tk.axpby(ctx, 1.0, ag, -1.0, ag)
+    tz, _ = tk.tucker_truncate(ctx, zg, 1e-6)
+    assert abs(tk.dot(ctx, tz, tz)) < 1e-28 * T.dot(a, a)
+    # an exactly empty tensor truncates to rank 0
+    e = tk.Tucker.from_host(ctx, np.zeros((0, 0, 0)), [np.zeros((m, 0)) for m in n])
+    te, _ = tk.tucker_truncate(ctx, e, 1e-6)
+    assert te.shape()[1] == (0, 0, 0)
+
+
+# --- preconditioner (Algorithm 4) --------------------------------------------------------
+
+@pytest.mark.parametrize("n_el,p", [(16, 2), (16, 3), (32, 4), (128, 3), (64, 5)])
+def test_fd_precond(ctx, n_el, p):
+    tk, prob = lib_modules()
+    say(f"fd_precond n_el={n_el} p={p}")
+    P_or = ofd.LowRankFD(n_el, p, 0.1)
+    Pg = tk.Preconditioner.create(ctx, n_el, p, 0.1)
+    info = Pg.info()
+    assert info["R_P"] == P_or.R_P
+    np.testing.assert_allclose(info["alpha"], P_or.alpha, rtol=1e-9)
+    np.testing.assert_allclose(info["omega"], P_or.omega, rtol=1e-9)
+    assert abs(info["lam_min"] - P_or.lam_min) < 1e-12 * P_or.lam_min
+    n = n_el + p - 2
+    s = rnd(n, (3, 5, 2), 7)
+    v = tk.fd_precond(ctx, Pg, upload(ctx, s))
+    got = to_oracle(v)
+    ref = P_or.apply(s)
+    assert got.m == ref.m
+    for k in range(3):
+        scale = np.abs(ref.U[k]).max()
+        np.testing.assert_allclose(got.U[k], ref.U[k], rtol=0, atol=1e-9 * scale)
+    for (cg, _, og), (cr, _, orr) in zip(got.blocks, ref.blocks):
+        assert og == orr and abs(cg - cr) <= 1e-9 * abs(cr)
+
+
+# --- TPCG (Algorithm 5) -----------------------------------------------------------------
+
+def test_tpcg_small_cube(ctx):
+    tk, prob = lib_modules()
+    say("tpcg small cube (p=2, n_el=16)")
+    w = W.config_small()
+    x, info = tk.tpcg_solve(ctx, prob.operator(ctx, w), prob.preconditioner(ctx, w), prob.rhs(ctx, w),
+                            tol=w.tol, eps_min=w.eps_min)
+    op = oprob.operator(w)
+    f = oprob.rhs(w)
+    xr, it, res = fullpcg.pcg_exact_fd(w, op, f.full(), 1e-14)
+    say(f"   iters={info['iters']} relres={info['relres']:.2e} rank={info['rank']}")
+    assert info["converged"] and info["rank"] == (1, 1, 1)
+    assert rel(to_oracle_plain(x).full(), xr) < 1e-10
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_tpcg_weighted_tiny(ctx, p):
+    tk, prob = lib_modules()
+    say(f"tpcg weighted tiny p={p}")
+    w = W.weighted_cp(8, p, 6, 2, 101, 102)
+    x, info = tk.tpcg_solve(ctx, prob.operator(ctx, w), prob.preconditioner(ctx, w), prob.rhs(ctx, w),
+                            tol=1e-8)
+    op = oprob.operator(w)
+    f = oprob.rhs(w)
+    xd = fullpcg.dense_solve(op, f.full())
+    xo, io = otpcg.tpcg(op, ofd.LowRankFD(8, p, 0.1), f, tol=1e-8)
+    say(f"   gpu iters={info['iters']} oracle iters={io.iters} relres={info['relres']:.2e}")
+    assert info["converged"]
+    assert rel(to_oracle_plain(x).full(), xd) < 1e-6
+    assert abs(info["iters"] - io.iters) <= max(2, 0.1 * io.iters)
