@@ -11,10 +11,15 @@ namespace gpu {
 void band_apply(hipStream_t s, int n, int m, int nmat, int p, const double* band,
                 const double* Y, int ldy, double* W, int ldw);
 
-// C = alpha op(A) op(B) + beta C, batched with element strides.
+// C = alpha op(A) op(B) + beta C, batched with element strides.  With
+// `part` (nsplit * M * N doubles) and nsplit > 1 (batch 1), K is split over
+// nsplit workgroup layers whose partial products are summed by a second
+// kernel in a fixed order (deterministic).
+int dgemm_split_count(int M, int N, int K);
 void dgemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
            const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
-           double beta, double* C, int ldc, long long sC, int batch = 1);
+           double beta, double* C, int ldc, long long sC, int batch = 1, double* part = nullptr,
+           int nsplit = 1);
 
 // Householder QR of up to 3 independent tall matrices (m <= n), one
 // workgroup each.  A (n x m, ld n) is overwritten by the reflectors; R (m x m)
@@ -29,10 +34,16 @@ struct QrJob {
 void householder_qr(hipStream_t s, const QrJob* jobs, int njobs);
 
 // Symmetric eigendecomposition G = V diag(w) V^T of an a x a matrix by
-// parallel cyclic Jacobi in one workgroup (LDS-resident for a <= 140).
-// `work` must hold (a+1)^2 doubles when a > 140; the number of sweeps is
-// written to *sweeps (device int, may be null).
-void jacobi_eig(hipStream_t s, double* G, int a, double* V, double* w, double* work, int* sweeps);
+// parallel cyclic Jacobi in one workgroup (LDS-resident for a <= 140) whose
+// rotations are recorded in `rot` (jacobi_rot_capacity(a) entries) and then
+// replayed on the identity by many workgroups to form V.  `work` must hold
+// (a+1)^2 doubles when a > 140.  rounds[0] = rounds executed, rounds[1] =
+// sweeps (device ints).  Couplings too small to move 1e-6 of the
+// truncation budget eps^2 norm2 / 3 (norm2: device scalar, or the trace of G
+// when null) between the kept and discarded directions are not rotated away.
+size_t jacobi_rot_capacity(int a);
+void jacobi_eig(hipStream_t s, double* G, int a, double* V, double* w, double* work, double2* rot,
+                int* rounds, double eps, const double* norm2);
 
 // e[j] = sum_i P[i, j]^2 for the a columns of P (rows x a, ld rows)
 void column_energy(hipStream_t s, const double* P, int rows, int a, double* e);

@@ -96,17 +96,29 @@ void band_apply(hipStream_t s, int n, int m, int nmat, int p, const double* band
 
 constexpr int BM = 64, BN = 64, BK = 16;
 
+// With `part` set, blockIdx.z selects the K range [z*kchunk, (z+1)*kchunk)
+// and alpha*op(A)op(B) over that range is written to part + z*M*N (ld M);
+// otherwise blockIdx.z is the batch index.
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha,
                                                const double* __restrict__ A, int lda, long long sA,
                                                const double* __restrict__ B, int ldb, long long sB,
                                                double beta, double* __restrict__ C, int ldc,
-                                               long long sC) {
+                                               long long sC, int kchunk, double* __restrict__ part) {
   __shared__ double As[BK][BM + 1];
   __shared__ double Bs[BK][BN + 1];
-  A += sA * blockIdx.z;
-  B += sB * blockIdx.z;
-  C += sC * blockIdx.z;
+  int kbeg = 0, kend = K;
+  if (part) {
+    kbeg = blockIdx.z * kchunk;
+    kend = min(K, kbeg + kchunk);
+    C = part + (long long)blockIdx.z * M * N;
+    ldc = M;
+    beta = 0.0;
+  } else {
+    A += sA * blockIdx.z;
+    B += sB * blockIdx.z;
+    C += sC * blockIdx.z;
+  }
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int row0 = blockIdx.x * BM, col0 = blockIdx.y * BN;
   double acc[4][4];
@@ -114,7 +126,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     // A tile: op(A)[row0 + i][k0 + kk]
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
@@ -123,7 +135,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
       if (!TA) { i = e & (BM - 1); kk = e >> 6; } else { kk = e & (BK - 1); i = e >> 4; }
       const int gr = row0 + i, gk = k0 + kk;
       double v = 0.0;
-      if (gr < M && gk < K) v = TA ? A[gk + (long long)gr * lda] : A[gr + (long long)gk * lda];
+      if (gr < M && gk < kend) v = TA ? A[gk + (long long)gr * lda] : A[gr + (long long)gk * lda];
       As[kk][i] = v;
     }
     // B tile: op(B)[k0 + kk][col0 + j]
@@ -134,7 +146,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
       if (!TB) { kk = e & (BK - 1); j = e >> 4; } else { j = e & (BN - 1); kk = e >> 6; }
       const int gc = col0 + j, gk = k0 + kk;
       double v = 0.0;
-      if (gc < N && gk < K) v = TB ? B[gc + (long long)gk * ldb] : B[gk + (long long)gc * ldb];
+      if (gc < N && gk < kend) v = TB ? B[gc + (long long)gk * ldb] : B[gk + (long long)gc * ldb];
       Bs[kk][j] = v;
     }
     __syncthreads();
@@ -166,9 +178,28 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
   }
 }
 
+__global__ __launch_bounds__(256) void k_splitk_reduce(int M, int N, int nsplit, const double* __restrict__ part,
+                                                       double beta, double* __restrict__ C, int ldc) {
+  const long long MN = (long long)M * N;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < MN; e += 256LL * gridDim.x) {
+    double acc = 0.0;
+    for (int z = 0; z < nsplit; ++z) acc += part[z * MN + e];
+    const int i = int(e % M), j = int(e / M);
+    double* cp = C + i + (long long)j * ldc;
+    *cp = (beta == 0.0) ? acc : acc + beta * (*cp);
+  }
+}
+
+int dgemm_split_count(int M, int N, int K) {
+  const long long tiles = (long long)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  if (tiles >= 128 || K < 1024) return 1;
+  long long ns = std::min<long long>(K / 256, 256 / std::max<long long>(tiles, 1));
+  return (int)std::max<long long>(1, std::min<long long>(ns, 64));
+}
+
 void dgemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
            const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
-           double beta, double* C, int ldc, long long sC, int batch) {
+           double beta, double* C, int ldc, long long sC, int batch, double* part, int nsplit) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   if (K <= 0) {
     if (beta == 1.0) return;
@@ -177,12 +208,26 @@ void dgemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
       for (int j = 0; j < N; ++j) scale_copy(s, C + sC * b + (long long)j * ldc, M, beta, C + sC * b + (long long)j * ldc);
     return;
   }
-  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, batch);
-  if (!ta && !tb) hipLaunchKernelGGL((k_dgemm<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
-  else if (ta && !tb) hipLaunchKernelGGL((k_dgemm<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
-  else if (!ta && tb) hipLaunchKernelGGL((k_dgemm<false, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
-  else hipLaunchKernelGGL((k_dgemm<true, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC);
+  int kchunk = K;
+  int gz = batch;
+  if (part && nsplit > 1 && batch == 1) {
+    kchunk = ((K + nsplit - 1) / nsplit + BK - 1) / BK * BK;
+    gz = (K + kchunk - 1) / kchunk;
+  } else {
+    part = nullptr;
+  }
+  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, gz);
+  if (!ta && !tb) hipLaunchKernelGGL((k_dgemm<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
+  else if (ta && !tb) hipLaunchKernelGGL((k_dgemm<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
+  else if (!ta && tb) hipLaunchKernelGGL((k_dgemm<false, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
+  else hipLaunchKernelGGL((k_dgemm<true, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
   check_launch("dgemm");
+  if (part) {
+    const long long MN = (long long)M * N;
+    const int nb = (int)std::min<long long>(1024, (MN + 255) / 256);
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(nb), dim3(256), 0, s, M, N, gz, part, beta, C, ldc);
+    check_launch("splitk_reduce");
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -272,12 +317,40 @@ void householder_qr(hipStream_t s, const QrJob* jobs, int njobs) {
 
 constexpr int kJacLdsMax = 140;
 constexpr int kJacThreads = 1024;
+constexpr int kJacMaxSweeps = 40;
 
+// round-robin pairing: in round r of a sweep over P (even) indices, slot t
+// pairs (p, q); every pair occurs once per sweep of P-1 rounds
+__device__ inline void jac_pair(int r, int t, int P, int& p, int& q) {
+  if (t == 0) { p = r % (P - 1); q = P - 1; }
+  else { p = (r + t) % (P - 1); q = (r - t + P - 1) % (P - 1); }
+  if (p > q) { const int x = p; p = q; q = x; }
+}
+
+// Cyclic Jacobi on S = G (a x a, padded to even P), one workgroup.  The
+// rotations are not applied to an eigenvector matrix here; they are written
+// to `rot` (one (c, s) per slot and round) and replayed by k_jacobi_vectors.
+// A rotation is skipped when
+//  * |a_pq| <= 1e-13 sqrt(|a_pp a_qq|) (relative accuracy criterion,
+//    tolerance about n u), or
+//  * |a_pq| is below the rounding noise of the Gram matrix itself,
+//    1e-15 max_i |a_ii| (couplings at that level carry no information, and
+//    rotating the resulting cluster of noise-level eigenvalues with large
+//    angles only scrambles the couplings that still need removing), or
+//  * a_pq^2 <= leak * max(|a_pp|, |a_qq|) with leak = 1e-6 budget / a: the
+//    energy that the coupling can move between the two directions is then
+//    a millionth of the truncation budget spread over all directions (the
+//    kept subspace tilts by at most ~1e-3 eps ||Z|| in total).  The
+//    caller measures the energy of every direction of the returned basis
+//    directly, so an unconverged coupling below this level can only cost a
+//    marginal rank, never accuracy.  budget = eps^2 norm2 / 3 with norm2 =
+//    *norm2 if given, else the trace of G.
 __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict__ G, int a,
-                                                        double* __restrict__ V,
                                                         double* __restrict__ w,
                                                         double* __restrict__ work,
-                                                        int* __restrict__ sweeps_out) {
+                                                        double2* __restrict__ rot,
+                                                        int* __restrict__ rounds_out, double eps,
+                                                        const double* __restrict__ norm2) {
   extern __shared__ double smem[];
   const int P = (a + 1) & ~1;
   const int H = P / 2;
@@ -288,35 +361,41 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   int* pp = reinterpret_cast<int*>(sn + H);
   int* qq = pp + H;
   __shared__ int rotated;
-  __shared__ double dmax;
+  __shared__ double dmax, leak;
   for (int e = threadIdx.x; e < P * P; e += kJacThreads) {
     const int i = e % P, j = e / P;
     S[e] = (i < a && j < a) ? G[i + (long long)j * a] : 0.0;
   }
-  for (long long e = threadIdx.x; e < (long long)a * a; e += kJacThreads)
-    V[e] = ((e % a) == (e / a)) ? 1.0 : 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double nz = 0.0;
+    if (norm2) nz = *norm2;
+    else for (int i = 0; i < a; ++i) nz += S[i + i * P];
+    leak = 1e-6 * (eps * eps * fmax(nz, 0.0) / 3.0) / a;
+  }
   __syncthreads();
   int sweep = 0;
-  for (; sweep < 40; ++sweep) {
+  int round_total = 0;
+  for (; sweep < kJacMaxSweeps; ++sweep) {
     if (threadIdx.x == 0) {
+      rotated = 0;
       double dm = 0.0;
       for (int i = 0; i < a; ++i) dm = fmax(dm, fabs(S[i + i * P]));
       dmax = dm;
-      rotated = 0;
     }
     __syncthreads();
-    const double floor_abs = 1e-16 * dmax;
-    for (int r = 0; r < P - 1; ++r) {
+    const double floor_abs = 1e-15 * dmax;
+    for (int r = 0; r < P - 1; ++r, ++round_total) {
       for (int t = threadIdx.x; t < H; t += kJacThreads) {
         int p, q;
-        if (t == 0) { p = r % (P - 1); q = P - 1; }
-        else { p = (r + t) % (P - 1); q = (r - t + P - 1) % (P - 1); }
-        if (p > q) { const int x = p; p = q; q = x; }
+        jac_pair(r, t, P, p, q);
         double c = 1.0, s = 0.0;
         const double apq = S[p + q * P];
         if (q < a && apq != 0.0) {
           const double app = S[p + p * P], aqq = S[q + q * P];
-          if (!(fabs(apq) <= 1e-15 * sqrt(fabs(app * aqq)) || fabs(apq) <= floor_abs)) {
+          const double aa = fabs(apq);
+          if (!(aa <= 1e-13 * sqrt(fabs(app * aqq)) || aa <= floor_abs ||
+                aa * aa <= leak * fmax(fabs(app), fabs(aqq)))) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
@@ -328,6 +407,7 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
         sn[t] = s;
         pp[t] = p;
         qq[t] = q;
+        rot[(long long)round_total * H + t] = make_double2(c, s);
       }
       __syncthreads();
       // two-sided update of the 2x2 blocks (pair t1 rows, pair t2 columns)
@@ -336,44 +416,96 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
         const double c1 = cs[t1], s1 = sn[t1], c2 = cs[t2], s2 = sn[t2];
         if (s1 == 0.0 && s2 == 0.0) continue;
         const int p1 = pp[t1], q1 = qq[t1], p2 = pp[t2], q2 = qq[t2];
-        double xpp = S[p1 + p2 * P], xpq = S[p1 + q2 * P], xqp = S[q1 + p2 * P], xqq = S[q1 + q2 * P];
-        // rows: J1^T X
-        double ypp = c1 * xpp - s1 * xqp, ypq = c1 * xpq - s1 * xqq;
-        double yqp = s1 * xpp + c1 * xqp, yqq = s1 * xpq + c1 * xqq;
-        // columns: (J1^T X) J2
+        const double xpp = S[p1 + p2 * P], xpq = S[p1 + q2 * P], xqp = S[q1 + p2 * P], xqq = S[q1 + q2 * P];
+        const double ypp = c1 * xpp - s1 * xqp, ypq = c1 * xpq - s1 * xqq;
+        const double yqp = s1 * xpp + c1 * xqp, yqq = s1 * xpq + c1 * xqq;
         S[p1 + p2 * P] = c2 * ypp - s2 * ypq;
         S[p1 + q2 * P] = s2 * ypp + c2 * ypq;
         S[q1 + p2 * P] = c2 * yqp - s2 * yqq;
         S[q1 + q2 * P] = s2 * yqp + c2 * yqq;
       }
-      for (int e = threadIdx.x; e < a * H; e += kJacThreads) {
-        const int i = e % a, t2 = e / a;
-        const double s2 = sn[t2];
-        if (s2 == 0.0) continue;
-        const int p2 = pp[t2], q2 = qq[t2];
-        if (q2 >= a) continue;
-        const double c2 = cs[t2];
-        const double vp = V[i + (long long)p2 * a], vq = V[i + (long long)q2 * a];
-        V[i + (long long)p2 * a] = c2 * vp - s2 * vq;
-        V[i + (long long)q2 * a] = s2 * vp + c2 * vq;
+      __syncthreads();
+    }
+    // every thread reads the flag before thread 0 may reset it
+    const bool done = (rotated == 0);
+    __syncthreads();
+    if (done) { ++sweep; break; }
+  }
+  for (int i = threadIdx.x; i < a; i += kJacThreads) w[i] = S[i + i * P];
+  if (threadIdx.x == 0) {
+    rounds_out[0] = round_total;
+    rounds_out[1] = sweep;
+  }
+}
+
+// V = product of the recorded rotations applied to the identity, replayed
+// for a slice of kVRows rows per workgroup held in LDS (rows of V are
+// independent: row i of V J is row i of V times J).
+constexpr int kVRows = 8;
+constexpr int kVChunk = 32;  // rounds of rotations staged in LDS at a time
+
+__global__ __launch_bounds__(256) void k_jacobi_vectors(int a, const double2* __restrict__ rot,
+                                                        const int* __restrict__ rounds,
+                                                        double* __restrict__ V, int chunk) {
+  extern __shared__ double vr[];  // kVRows x P rows of V, then chunk x H rotations
+  const int P = (a + 1) & ~1, H = P / 2;
+  double2* rc = reinterpret_cast<double2*>(vr + kVRows * P);
+  const int row0 = blockIdx.x * kVRows;
+  for (int e = threadIdx.x; e < kVRows * P; e += 256) {
+    const int lr = e / P, j = e % P;
+    vr[e] = (row0 + lr == j) ? 1.0 : 0.0;
+  }
+  const int nr = rounds[0];
+  for (int c0 = 0; c0 < nr; c0 += chunk) {
+    const int nc = min(chunk, nr - c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nc * H; e += 256) rc[e] = rot[(long long)c0 * H + e];
+    __syncthreads();
+    for (int k = 0; k < nc; ++k) {
+      const int r = (c0 + k) % (P - 1);
+      for (int e = threadIdx.x; e < kVRows * H; e += 256) {
+        const int lr = e / H, t = e % H;
+        const double2 cs = rc[k * H + t];
+        if (cs.y == 0.0) continue;
+        int p, q;
+        jac_pair(r, t, P, p, q);
+        double* row = vr + lr * P;
+        const double vp = row[p], vq = row[q];
+        row[p] = cs.x * vp - cs.y * vq;
+        row[q] = cs.y * vp + cs.x * vq;
       }
       __syncthreads();
     }
-    if (rotated == 0) break;
-    __syncthreads();
   }
-  for (int i = threadIdx.x; i < a; i += kJacThreads) w[i] = S[i + i * P];
-  if (threadIdx.x == 0 && sweeps_out) *sweeps_out = sweep + 1;
+  __syncthreads();
+  for (int e = threadIdx.x; e < kVRows * a; e += 256) {
+    const int lr = e / a, j = e % a;
+    const int i = row0 + lr;
+    if (i < a) V[i + (long long)j * a] = vr[lr * P + j];
+  }
 }
 
-void jacobi_eig(hipStream_t s, double* G, int a, double* V, double* w, double* work, int* sweeps) {
+size_t jacobi_rot_capacity(int a) {
+  const int P = (a + 1) & ~1;
+  return (size_t)kJacMaxSweeps * (P - 1) * (P / 2);
+}
+
+void jacobi_eig(hipStream_t s, double* G, int a, double* V, double* w, double* work, double2* rot,
+                int* rounds, double eps, const double* norm2) {
   if (a <= 0) return;
   const int P = (a + 1) & ~1;
   size_t lds;
   if (P <= kJacLdsMax) lds = sizeof(double) * (P * P + P) + sizeof(int) * P;
   else lds = sizeof(double) * P + sizeof(int) * P;
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(kJacThreads), lds, s, G, a, V, w, work, sweeps);
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(kJacThreads), lds, s, G, a, w, work, rot, rounds, eps, norm2);
   check_launch("jacobi_eig");
+  const int nb = (a + kVRows - 1) / kVRows;
+  // stage as many rounds as fit next to the row slice in at most ~150 KB of LDS
+  const long long room = 150000LL - (long long)sizeof(double) * kVRows * P;
+  const int chunk = (int)std::max<long long>(1, std::min<long long>(kVChunk, room / ((long long)sizeof(double2) * (P / 2))));
+  const size_t vlds = sizeof(double) * kVRows * P + sizeof(double2) * chunk * (P / 2);
+  hipLaunchKernelGGL(k_jacobi_vectors, dim3(nb), dim3(256), vlds, s, a, rot, rounds, V, chunk);
+  check_launch("jacobi_vectors");
 }
 
 // ---------------------------------------------------------------------------

@@ -258,7 +258,11 @@ static void gemm(tk_ctx* ctx, bool ta, bool tb, int M, int N, int K, double alph
                  const double* B, int ldb, double beta, double* C, int ldc) {
   Prof pr(ctx, PK_GEMM, 8.0 * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1)),
           2.0 * M * N * (double)K);
-  gpu::dgemm(ctx->stream, ta, tb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0);
+  const int ns = gpu::dgemm_split_count(M, N, K);
+  BufP part;
+  if (ns > 1) part = alloc(ctx, (size_t)ns * M * N);
+  gpu::dgemm(ctx->stream, ta, tb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1,
+             part ? part->p : nullptr, ns);
 }
 
 // ---------------------------------------------------------------------------
@@ -461,10 +465,12 @@ static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double*
     BufP V = alloc(ctx, (size_t)a * a), w = alloc(ctx, (size_t)a);
     BufP work;
     if (((a + 1) & ~1) > 140) work = alloc(ctx, (size_t)(a + 1) * (a + 1));
+    BufP rot = alloc(ctx, 2 * gpu::jacobi_rot_capacity(a));
     int* sweeps_dev = reinterpret_cast<int*>(ctx->sel->p) + 2100;
     {
       Prof pr(ctx, PK_JACOBI, 8.0 * 2.0 * a * (double)a, 0.0);
-      gpu::jacobi_eig(ctx->stream, G->p, a, V->p, w->p, work ? work->p : nullptr, sweeps_dev);
+      gpu::jacobi_eig(ctx->stream, G->p, a, V->p, w->p, work ? work->p : nullptr,
+                      reinterpret_cast<double2*>(rot->p), sweeps_dev, eps, k == 0 ? nullptr : norm2);
     }
     // P = A^T V (bc x a): columns are the mode-k coordinates in the eigenbasis
     BufP Pm = alloc(ctx, (size_t)bc * a);
@@ -479,13 +485,14 @@ static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double*
     int hsel = 0, hsweeps = 0;
     double hdisc = 0.0;
     HIPCHK(hipMemcpyAsync(&hsel, sel, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    if (ctx->prof) HIPCHK(hipMemcpyAsync(&hsweeps, sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    if (ctx->prof) HIPCHK(hipMemcpyAsync(&hsweeps, sweeps_dev + 1, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipMemcpyAsync(&hdisc, disc, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     if (k == 0) HIPCHK(hipMemcpyAsync(&P.norm2, norm2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     sync(ctx);
     if (ctx->prof) {
       // flops of the parallel Jacobi sweeps: (P-1) rounds of (P/2)^2 two-sided
-      // 2x2 block updates (24 flops) and a*P/2 eigenvector pairs (6 flops)
+      // 2x2 block updates (24 flops) and their replay on the a x a
+      // eigenvector matrix (a*P/2 pairs of 6 flops)
       const double Pd = double((a + 1) & ~1);
       ctx->p_flops[PK_JACOBI] += hsweeps * (Pd - 1.0) * (6.0 * Pd * Pd + 3.0 * a * Pd);
     }

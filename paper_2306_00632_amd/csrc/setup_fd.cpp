@@ -257,7 +257,7 @@ bool fd_direction_setup(int n_el, int p, double coef, FdDirection& d, std::strin
         return false;
       }
       for (size_t c = 0; c < cand.size(); ++c)
-        if (std::fabs(xs[c]) > 1e-13) coeffs.push_back({cand[c], xs[c]});
+        if (std::fabs(xs[c]) > 1e-10) coeffs.push_back({cand[c], xs[c]});  // exact coefficients are O(1e-3) or more; drop least-squares noise
     }
     for (auto& lc : coeffs) {
       const int l = lc.first;

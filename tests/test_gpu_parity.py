@@ -4,10 +4,15 @@ against the FP64 oracle on the same seeded inputs.
 Tolerances (FP64 throughout the GPU path):
 * operator application and dots: elementwise relative 1e-12 (banded sums of
   at most 2p+1 products; GEMM reassociation only);
-* truncation: same ranks as the oracle's SVD-based ST-HOSVD, represented
-  tensors within 1e-10 relative (both are the sequentially truncated HOSVD of
-  the same core; the GPU takes singular directions from a Jacobi-diagonalised
-  Gram matrix and measures the discarded energy directly);
+* truncation: the contract of eq. (rel_estimate), ||y - T(y)|| <= eps ||y||,
+  exactly; the same ranks as the oracle's SVD-based ST-HOSVD; and agreement
+  with the oracle's truncated tensor to 5e-3 eps (plus 1e-10): the GPU takes
+  the singular directions from a Jacobi-diagonalised Gram matrix whose
+  rotations stop once a remaining coupling could move less than 1e-6 of the
+  truncation budget eps^2 ||Z||^2 / 3 (a tilt of the kept subspace of order
+  1e-3 eps ||Z||), and it measures the discarded energy of its basis
+  directly, so its output differs from the exact ST-HOSVD only far inside
+  the truncation error;
 * preconditioner: 1e-9 relative (the exponential-sum parameters of the
   library's and the oracle's independent Remez solvers agree to ~1e-11);
 * TPCG: relative solution error against the full-tensor reference
@@ -94,7 +99,7 @@ def _check_trunc(ctx, ysum_oracle, yg, eps):
     assert got.ranks == ref.ranks
     ny = T.norm(ysum_oracle)
     if ny > 0:
-        assert T.rel_diff(got, ref) < 1e-10 or T.norm(ref) == 0
+        assert T.rel_diff(got, ref) < 5e-3 * eps + 1e-10 or T.norm(ref) == 0
         # relative error bound of eq. (rel_estimate), measured without cancellation
         assert T.rel_diff(got, ysum_oracle) <= eps * (1 + 1e-8) + 1e-13
     for U in got.U:

@@ -1,0 +1,110 @@
+"""Host-side checks of libtk.so (no GPU needed): the library loads and
+exports every symbol include/tk.h declares, invalid arguments return error
+codes, and the host setup (1D B-spline matrices, Appendix B transform data,
+Remez exponential sums) agrees with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import bspline as obs
+from oracle import expsum as oexp
+from oracle import fd as ofd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def tk():
+    from paper_2306_00632_amd import tk as tkmod
+    if not os.path.exists(tkmod.LIB_PATH):
+        from paper_2306_00632_amd import build
+        build.build()
+    tkmod.lib()
+    return tkmod
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "tk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^(?:tk_status|void|const char\*)\s+(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_all_declared_symbols_exported(tk):
+    import ctypes
+    L = ctypes.CDLL(tk.LIB_PATH)
+    names = declared_functions()
+    assert "tucker_apply_op" in names and "fd_precond" in names and "tucker_truncate" in names \
+        and "tpcg_solve" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # the binding declares argument types for every exported entry point
+    assert set(names) <= set(tk.EXPORTS), sorted(set(names) - set(tk.EXPORTS))
+
+
+def test_invalid_arguments_return_errors(tk):
+    import ctypes as C
+    L = tk.lib()
+    band = np.zeros(10)
+    w = np.array([1.0, 0.0, 0.0, 0.0])
+    assert L.tk_assemble_1d(8, 0, 0, w.ctypes.data_as(tk.dp), band.ctypes.data_as(tk.dp)) == tk.TK_EINVAL
+    assert L.tk_assemble_1d(8, 2, 7, w.ctypes.data_as(tk.dp), band.ctypes.data_as(tk.dp)) == tk.TK_EINVAL
+    n = C.c_int32()
+    # n_el must exceed p and be a power of two for the FFT transform
+    assert L.tk_fd_direction_host(3, 3, 1.0, C.byref(n), None, None, None, None, None, None) == tk.TK_EINVAL
+    assert L.tk_fd_direction_host(48, 3, 1.0, C.byref(n), None, None, None, None, None, None) == tk.TK_EINVAL
+    assert L.tk_fd_direction_host(16, 3, -1.0, C.byref(n), None, None, None, None, None, None) == tk.TK_EINVAL
+    assert L.tk_expsum_host(0.5, 0.1, None, None, None, None, None) == tk.TK_ENUMERIC
+    assert L.tk_tucker_shape(None, None, None, None) == tk.TK_EINVAL
+
+
+@pytest.mark.parametrize("kind", ["mass", "stiff", "mixed10", "mixed01"])
+@pytest.mark.parametrize("p", [1, 2, 3, 5])
+def test_assemble_1d_matches_oracle(tk, kind, p):
+    w = (1.0, 0.5, 1.3, 0.4)
+    A = tk.band_to_dense(tk.assemble_1d(16, p, kind, w))
+    R = obs.matrix(16, p, kind, w)
+    assert np.abs(A - R).max() <= 1e-14 * np.abs(R).max()
+
+
+def test_load_vector_matches_oracle(tk):
+    sin = (0.0, 1.0, np.pi, -0.5 * np.pi)
+    np.testing.assert_allclose(tk.load_vector_1d(32, 3, sin), obs.load_vector(32, 3, sin), rtol=1e-13, atol=1e-17)
+
+
+@pytest.mark.parametrize("p,n_el", [(2, 16), (3, 16), (3, 64), (4, 32), (5, 16)])
+def test_appendix_b_transform_data_matches_oracle(tk, p, n_el):
+    """E * DST * diag(g) (the library's symbol-division form of V1 U1) equals
+    the oracle's interpolation-based V1 U1; V2 U2 spans the same operator."""
+    d = tk.fd_direction_host(n_el, p)
+    Ut, lam, P = ofd.approx_eig(n_el, p)
+    n1 = d["n1"]
+    j = np.arange(1, n1 + 1)
+    xi = np.arange(1, n_el) / n_el if p % 2 else (np.arange(n_el) + 0.5) / n_el
+    S = np.sin(np.pi * np.outer(xi, j))
+    V1U1 = d["E"] @ S @ np.diag(d["g"])
+    assert np.abs(V1U1 - Ut[:, :n1]).max() <= 1e-12 * np.abs(Ut[:, :n1]).max()
+    np.testing.assert_allclose(d["lam"], lam, rtol=1e-12)
+    if d["n2"]:
+        # the V_h2 eigenvalues come in nearly degenerate left/right pairs, so
+        # compare the operators V2U2 f(Lambda2) (V2U2)^T, not the vectors
+        t = 1.0 / lam[n1:].max()
+        A = Ut[:, n1:] @ np.diag(np.exp(-t * lam[n1:])) @ Ut[:, n1:].T
+        B = d["v2u2"] @ np.diag(np.exp(-t * d["lam"][n1:])) @ d["v2u2"].T
+        assert np.abs(A - B).max() <= 1e-11 * np.abs(A).max()
+    # E is sparse: one entry per interior row
+    nnz_rows = (d["E"] != 0).sum(axis=1)
+    assert nnz_rows[p + 1:-(p + 1)].max() == 1
+
+
+@pytest.mark.parametrize("M", [20.0, 256.0, 16384.0, 2.3843e4, 3.8149e5, 1.0486e6])
+def test_expsum_matches_oracle(tk, M):
+    d = tk.expsum_host(M, 0.1)
+    R, al, om, E, Ep = oexp.exp_sum_for(M, 0.1)
+    assert d["R"] == R
+    assert abs(d["err"] - E) <= 1e-8 * E
+    np.testing.assert_allclose(d["alpha"], al, rtol=1e-8)
+    np.testing.assert_allclose(d["omega"], om, rtol=1e-8)
+    assert d["err"] <= 0.1 / M < d["err_prev"]

@@ -111,13 +111,22 @@ def config_small() -> Workload:
 
 def config_deformed() -> Workload:
     """Deformed-geometry Poisson stand-in: p = 3, n_el = 128 (129 dofs),
-    9 weighted Kronecker terms (seed 2002), rhs Tucker rank 5 (seed 2003)."""
-    return weighted_cp(128, 3, 9, 5, 2002, 2003,
-                       name="poisson_weighted9_p3_nel128_r5")
+    9 weighted Kronecker terms (seed 2002), rhs Tucker rank 5 (seed 2003).
+
+    The rhs factors are white noise, so the solution is nearly full rank at
+    tol = 1e-6; with the default floor eps_min = 0.1 tol the residual
+    stagnates near 2.5e-6 (the stagnation reported for the elasticity column
+    in Sec. 5.3), and the remedy given there, a lower eps_min, is applied:
+    eps_min = 1e-8."""
+    w = weighted_cp(128, 3, 9, 5, 2002, 2003, name="poisson_weighted9_p3_nel128_r5")
+    w.eps_min = 1e-8
+    return w
 
 
 def config_large() -> Workload:
     """Large single solve: p = 3, n_el = 512 (515 dofs), 12 weighted terms
-    (seed 3002), rhs Tucker rank 10 (seed 3003)."""
-    return weighted_cp(512, 3, 12, 10, 3002, 3003,
-                       name="poisson_weighted12_p3_nel512_r10")
+    (seed 3002), rhs Tucker rank 10 (seed 3003); eps_min as for the
+    deformed workload."""
+    w = weighted_cp(512, 3, 12, 10, 3002, 3003, name="poisson_weighted12_p3_nel512_r10")
+    w.eps_min = 1e-8
+    return w
