@@ -186,6 +186,17 @@ tk_status tk_prec_direction(const tk_prec* P, int32_t k, int32_t* n, int32_t* n1
 tk_status tucker_truncate(tk_ctx* ctx, const tk_tucker* y, double eps, tk_tucker** out,
                           double* discarded);
 
+/* Symmetric eigendecomposition G = V diag(w) V^T (the ST-HOSVD building block
+ * of tucker_truncate) of an a x a matrix, a <= 2048, by the library's
+ * parallel Jacobi kernel.  G, V (a x a, column-major) and w (a) are device
+ * memory owned by the caller; G is not modified.  eps > 0 lets rotations
+ * stop once a remaining coupling could move less than 1e-6 of the energy
+ * eps^2 trace(G)/3 (the truncation budget); eps = 0 diagonalises to the
+ * rounding level.  `sweeps` (host, may be NULL) receives the sweep count.
+ * Eigenvalues are not sorted.  Synchronises when `sweeps` is given. */
+tk_status tk_sym_eig(tk_ctx* ctx, const double* G, int32_t a, double eps, double* V, double* w,
+                     int32_t* sweeps);
+
 /* ---- solver (Algorithm 5) -------------------------------------------------- */
 
 typedef struct {

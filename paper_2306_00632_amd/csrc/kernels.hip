@@ -356,10 +356,8 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   const int H = P / 2;
   const bool in_lds = P <= kJacLdsMax;
   double* S = in_lds ? smem : work;
-  double* cs = in_lds ? smem + P * P : smem;
-  double* sn = cs + H;
-  int* pp = reinterpret_cast<int*>(sn + H);
-  int* qq = pp + H;
+  double2* csn = reinterpret_cast<double2*>(in_lds ? smem + P * P : smem);  // (c, s) per slot
+  int2* pq = reinterpret_cast<int2*>(csn + H);                              // (p, q) per slot
   __shared__ int rotated;
   __shared__ double dmax, leak;
   for (int e = threadIdx.x; e < P * P; e += kJacThreads) {
@@ -403,19 +401,19 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
             rotated = 1;
           }
         }
-        cs[t] = c;
-        sn[t] = s;
-        pp[t] = p;
-        qq[t] = q;
+        csn[t] = make_double2(c, s);
+        pq[t] = make_int2(p, q);
         rot[(long long)round_total * H + t] = make_double2(c, s);
       }
       __syncthreads();
       // two-sided update of the 2x2 blocks (pair t1 rows, pair t2 columns)
       for (int e = threadIdx.x; e < H * H; e += kJacThreads) {
         const int t1 = e % H, t2 = e / H;
-        const double c1 = cs[t1], s1 = sn[t1], c2 = cs[t2], s2 = sn[t2];
+        const double2 r1 = csn[t1], r2 = csn[t2];
+        const double c1 = r1.x, s1 = r1.y, c2 = r2.x, s2 = r2.y;
         if (s1 == 0.0 && s2 == 0.0) continue;
-        const int p1 = pp[t1], q1 = qq[t1], p2 = pp[t2], q2 = qq[t2];
+        const int2 i1 = pq[t1], i2 = pq[t2];
+        const int p1 = i1.x, q1 = i1.y, p2 = i2.x, q2 = i2.y;
         const double xpp = S[p1 + p2 * P], xpq = S[p1 + q2 * P], xqp = S[q1 + p2 * P], xqq = S[q1 + q2 * P];
         const double ypp = c1 * xpp - s1 * xqp, ypq = c1 * xpq - s1 * xqq;
         const double yqp = s1 * xpp + c1 * xqp, yqq = s1 * xpq + c1 * xqq;
@@ -438,51 +436,50 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   }
 }
 
-// V = product of the recorded rotations applied to the identity, replayed
-// for a slice of kVRows rows per workgroup held in LDS (rows of V are
-// independent: row i of V J is row i of V times J).
-constexpr int kVRows = 8;
+// V = product of the recorded rotations applied to the identity.  Row i of
+// V J is row i of V times J, so rows are independent: every wavefront owns
+// one row (in LDS) and replays all rounds on it with its lanes taking the
+// pairs of a round; only the staging of rotation chunks needs a workgroup
+// barrier.  Within a wavefront, LDS accesses are performed in program order,
+// so a round sees the previous round's values once the wave has waited for
+// its own LDS operations.
+constexpr int kVWaves = 8;   // rows (wavefronts) per workgroup
 constexpr int kVChunk = 32;  // rounds of rotations staged in LDS at a time
 
-__global__ __launch_bounds__(256) void k_jacobi_vectors(int a, const double2* __restrict__ rot,
-                                                        const int* __restrict__ rounds,
-                                                        double* __restrict__ V, int chunk) {
-  extern __shared__ double vr[];  // kVRows x P rows of V, then chunk x H rotations
+__global__ __launch_bounds__(64 * kVWaves) void k_jacobi_vectors(int a, const double2* __restrict__ rot,
+                                                                 const int* __restrict__ rounds,
+                                                                 double* __restrict__ V, int chunk) {
+  extern __shared__ double vr[];  // kVWaves x P rows of V, then chunk x H rotations
   const int P = (a + 1) & ~1, H = P / 2;
-  double2* rc = reinterpret_cast<double2*>(vr + kVRows * P);
-  const int row0 = blockIdx.x * kVRows;
-  for (int e = threadIdx.x; e < kVRows * P; e += 256) {
-    const int lr = e / P, j = e % P;
-    vr[e] = (row0 + lr == j) ? 1.0 : 0.0;
-  }
+  double2* rc = reinterpret_cast<double2*>(vr + kVWaves * P);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * kVWaves + wv;  // row of V owned by this wavefront
+  double* row = vr + wv * P;
+  for (int j = lane; j < P; j += 64) row[j] = (i == j) ? 1.0 : 0.0;
   const int nr = rounds[0];
   for (int c0 = 0; c0 < nr; c0 += chunk) {
     const int nc = min(chunk, nr - c0);
     __syncthreads();
-    for (int e = threadIdx.x; e < nc * H; e += 256) rc[e] = rot[(long long)c0 * H + e];
+    for (int e = threadIdx.x; e < nc * H; e += 64 * kVWaves) rc[e] = rot[(long long)c0 * H + e];
     __syncthreads();
     for (int k = 0; k < nc; ++k) {
       const int r = (c0 + k) % (P - 1);
-      for (int e = threadIdx.x; e < kVRows * H; e += 256) {
-        const int lr = e / H, t = e % H;
+      for (int t = lane; t < H; t += 64) {
         const double2 cs = rc[k * H + t];
         if (cs.y == 0.0) continue;
         int p, q;
         jac_pair(r, t, P, p, q);
-        double* row = vr + lr * P;
         const double vp = row[p], vq = row[q];
         row[p] = cs.x * vp - cs.y * vq;
         row[q] = cs.y * vp + cs.x * vq;
       }
-      __syncthreads();
+      // order this round's LDS writes before the next round's reads (same wave)
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+      __builtin_amdgcn_wave_barrier();
     }
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kVRows * a; e += 256) {
-    const int lr = e / a, j = e % a;
-    const int i = row0 + lr;
-    if (i < a) V[i + (long long)j * a] = vr[lr * P + j];
-  }
+  if (i < a)
+    for (int j = lane; j < a; j += 64) V[i + (long long)j * a] = row[j];
 }
 
 size_t jacobi_rot_capacity(int a) {
@@ -495,16 +492,16 @@ void jacobi_eig(hipStream_t s, double* G, int a, double* V, double* w, double* w
   if (a <= 0) return;
   const int P = (a + 1) & ~1;
   size_t lds;
-  if (P <= kJacLdsMax) lds = sizeof(double) * (P * P + P) + sizeof(int) * P;
-  else lds = sizeof(double) * P + sizeof(int) * P;
+  if (P <= kJacLdsMax) lds = sizeof(double) * P * P + sizeof(double2) * (P / 2) + sizeof(int2) * (P / 2);
+  else lds = sizeof(double2) * (P / 2) + sizeof(int2) * (P / 2);
   hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(kJacThreads), lds, s, G, a, w, work, rot, rounds, eps, norm2);
   check_launch("jacobi_eig");
-  const int nb = (a + kVRows - 1) / kVRows;
-  // stage as many rounds as fit next to the row slice in at most ~150 KB of LDS
-  const long long room = 150000LL - (long long)sizeof(double) * kVRows * P;
+  const int nb = (a + kVWaves - 1) / kVWaves;
+  // stage as many rounds as fit next to the rows in at most ~150 KB of LDS
+  const long long room = 150000LL - (long long)sizeof(double) * kVWaves * P;
   const int chunk = (int)std::max<long long>(1, std::min<long long>(kVChunk, room / ((long long)sizeof(double2) * (P / 2))));
-  const size_t vlds = sizeof(double) * kVRows * P + sizeof(double2) * chunk * (P / 2);
-  hipLaunchKernelGGL(k_jacobi_vectors, dim3(nb), dim3(256), vlds, s, a, rot, rounds, V, chunk);
+  const size_t vlds = sizeof(double) * kVWaves * P + sizeof(double2) * chunk * (P / 2);
+  hipLaunchKernelGGL(k_jacobi_vectors, dim3(nb), dim3(64 * kVWaves), vlds, s, a, rot, rounds, V, chunk);
   check_launch("jacobi_vectors");
 }
 

@@ -1171,6 +1171,31 @@ tk_status tk_prof_read(tk_ctx* ctx, int32_t kind, int64_t* launches, double* ms,
   });
 }
 
+tk_status tk_sym_eig(tk_ctx* ctx, const double* G, int32_t a, double eps, double* V, double* w,
+                     int32_t* sweeps) {
+  if (!ctx || !G || !V || !w || a < 1 || a > 2048 || !(eps >= 0.0)) return TK_EINVAL;
+  return guarded(ctx, [&]() {
+    BufP Gc = alloc(ctx, (size_t)a * a);
+    d2d(ctx, Gc->p, G, (size_t)a * a);
+    BufP work;
+    if (((a + 1) & ~1) > 140) work = alloc(ctx, (size_t)(a + 1) * (a + 1));
+    BufP rot = alloc(ctx, 2 * gpu::jacobi_rot_capacity(a));
+    int* rounds = reinterpret_cast<int*>(ctx->sel->p) + 2100;
+    {
+      Prof pr(ctx, PK_JACOBI, 8.0 * 2.0 * a * (double)a, 0.0);
+      gpu::jacobi_eig(ctx->stream, Gc->p, a, V, w, work ? work->p : nullptr,
+                      reinterpret_cast<double2*>(rot->p), rounds, eps, nullptr);
+    }
+    if (sweeps) {
+      int h = 0;
+      HIPCHK(hipMemcpyAsync(&h, rounds + 1, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+      sync(ctx);
+      *sweeps = h;
+    }
+    return TK_OK;
+  });
+}
+
 void tk_tpcg_defaults(tk_tpcg_params* p) {
   if (!p) return;
   p->tol = 1e-6;

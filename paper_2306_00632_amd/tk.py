@@ -72,6 +72,7 @@ EXPORTS = {
     "fd_precond": (C.c_int32, [vp, vp, vp, C.POINTER(vp)]),
     "tucker_truncate": (C.c_int32, [vp, vp, C.c_double, C.POINTER(vp), dp]),
     "tk_tpcg_defaults": (None, [C.POINTER(TpcgParams)]),
+    "tk_sym_eig": (C.c_int32, [vp, vp, C.c_int32, C.c_double, vp, vp, i32p]),
     "tk_prof_enable": (C.c_int32, [vp, C.c_int32]),
     "tk_prof_reset": (C.c_int32, [vp]),
     "tk_prof_read": (C.c_int32, [vp, C.c_int32, i64p, dp, dp, dp]),
@@ -396,6 +397,14 @@ def axpby(ctx, a, x: Tucker, b, y: Tucker) -> Tucker:
     h = vp()
     ctx.check(lib().tk_tucker_axpby(ctx.h, a, x.h, b, y.h, C.byref(h)), "tk_tucker_axpby")
     return Tucker(ctx, h)
+
+
+def sym_eig(ctx, G_dev, a: int, V_dev, w_dev, eps: float = 0.0) -> int:
+    """Eigendecomposition of a device a x a matrix into device V, w; returns sweeps."""
+    sw = C.c_int32()
+    ctx.check(lib().tk_sym_eig(ctx.h, vp(G_dev.data_ptr()), a, eps, vp(V_dev.data_ptr()),
+                               vp(w_dev.data_ptr()), C.byref(sw)), "tk_sym_eig")
+    return sw.value
 
 
 def tpcg_params(**kw) -> TpcgParams:
