@@ -186,16 +186,16 @@ tk_status tk_prec_direction(const tk_prec* P, int32_t k, int32_t* n, int32_t* n1
 tk_status tucker_truncate(tk_ctx* ctx, const tk_tucker* y, double eps, tk_tucker** out,
                           double* discarded);
 
-/* Symmetric eigendecomposition G = V diag(w) V^T (the ST-HOSVD building block
- * of tucker_truncate) of an a x a matrix, a <= 2048, by the library's
- * parallel Jacobi kernel.  G, V (a x a, column-major) and w (a) are device
- * memory owned by the caller; G is not modified.  eps > 0 lets rotations
- * stop once a remaining coupling could move less than 1e-6 of the energy
- * eps^2 trace(G)/3 (the truncation budget); eps = 0 diagonalises to the
- * rounding level.  `sweeps` (host, may be NULL) receives the sweep count.
- * Eigenvalues are not sorted.  Synchronises when `sweeps` is given. */
-tk_status tk_sym_eig(tk_ctx* ctx, const double* G, int32_t a, double eps, double* V, double* w,
-                     int32_t* sweeps);
+/* Symmetric eigendecomposition G = V diag(w) V^T of an a x a matrix,
+ * 1 <= a <= 2048: the building block of the ST-HOSVD in tucker_truncate
+ * (Sec. 2.3; the left singular vectors of a mode unfolding A are the
+ * eigenvectors of its Gram matrix A A^T).  Householder tridiagonalisation,
+ * Sturm-count multisection for the eigenvalues, inverse iteration and two
+ * Gram-Schmidt passes for the vectors.  G, V (a x a, column-major) and w (a)
+ * are device memory owned by the caller; G is not modified.  V has
+ * orthonormal columns ordered by descending eigenvalue, w is descending.
+ * Asynchronous on the context's stream. */
+tk_status tk_sym_eig(tk_ctx* ctx, const double* G, int32_t a, double* V, double* w);
 
 /* ---- solver (Algorithm 5) -------------------------------------------------- */
 
@@ -223,7 +223,7 @@ typedef struct {
 
 /* Kernel families timed with HIP events on the context's stream when
  * instrumentation is on (off by default; it adds two events per launch). */
-enum { TK_PROF_BAND = 0, TK_PROF_GEMM = 1, TK_PROF_QR = 2, TK_PROF_JACOBI = 3, TK_PROF_SELECT = 4,
+enum { TK_PROF_BAND = 0, TK_PROF_GEMM = 1, TK_PROF_QR = 2, TK_PROF_EIG = 3, TK_PROF_SELECT = 4,
        TK_PROF_FD_FORWARD = 5, TK_PROF_FD_BACKWARD = 6, TK_PROF_MISC = 7 };
 tk_status tk_prof_enable(tk_ctx* ctx, int32_t on);
 tk_status tk_prof_reset(tk_ctx* ctx);

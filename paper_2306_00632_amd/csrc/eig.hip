@@ -1,0 +1,854 @@
+// Symmetric eigendecomposition G = V diag(w) V^T of the Gram matrices of the
+// ST-HOSVD (Sec. 2.3, step 3 of Algorithm 1) on one device.
+//
+// Pipeline (five launches, no host synchronisation):
+//   tridiag        Householder reduction Q^T G Q = T (tridiagonal), one
+//                  workgroup; the matrix lives in registers for
+//                  a <= kTriLdsMax, in global memory beyond
+//   bisect         eigenvalues of T by Sturm-count multisection, one
+//                  wavefront per eigenvalue, 63 trial points per step
+//   invit          two steps of inverse iteration per eigenvalue (one
+//                  thread each, tridiagonal LU with partial pivoting, seeded
+//                  pseudo-random start vectors)
+//   mgs            modified Gram-Schmidt in descending eigenvalue order, a
+//                  second pass when the first met nearly parallel columns
+//                  (clusters of close eigenvalues), so the columns are
+//                  orthonormal to rounding level
+//   backtransform  V = Q X, one wavefront per column
+// The matrix is scaled by a power of two so that max |G_ij| is in [1, 2);
+// w is returned unscaled, in descending order.
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "kernels.h"
+
+namespace tk {
+namespace gpu {
+
+namespace {
+
+constexpr int kTriThreads = 1024;
+constexpr int kTriLdsMax = 136;  // a^2 + 10 a doubles fit in the 160 KB of LDS
+constexpr int kBisWaves = 4;
+constexpr int kInvThreads = 64;
+constexpr int kBackWaves = 8;
+
+void check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Cross-lane moves of a double through DPP on its two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Reductions over the 64 lanes of a wavefront (all lanes active), returned
+// to every lane: quad swaps (quad_perm 1,0,3,2 and 2,3,0,1), half-row and
+// row mirrors leave each 16-lane row holding its total in every lane; the
+// four row totals are then combined in a fixed order, so the result is the
+// same in every lane and from run to run.
+#define TK_WAVE_REDUCE(NAME, OP)                                                              \
+  __device__ __forceinline__ double NAME(double v) {                                          \
+    v = OP(v, dpp_move<0xB1>(v));                                                              \
+    v = OP(v, dpp_move<0x4E>(v));                                                              \
+    v = OP(v, dpp_move<0x141>(v));                                                             \
+    v = OP(v, dpp_move<0x140>(v));                                                             \
+    return OP(OP(lane_value(v, 0), lane_value(v, 16)), OP(lane_value(v, 32), lane_value(v, 48))); \
+  }
+
+__device__ __forceinline__ double op_add(double x, double y) { return x + y; }
+__device__ __forceinline__ double op_max(double x, double y) { return fmax(x, y); }
+__device__ __forceinline__ double op_min(double x, double y) { return fmin(x, y); }
+TK_WAVE_REDUCE(wave_sum, op_add)
+TK_WAVE_REDUCE(wave_max, op_max)
+TK_WAVE_REDUCE(wave_min, op_min)
+#undef TK_WAVE_REDUCE
+
+// 1/q to full double precision: hardware reciprocal and two Newton steps
+// (|q| is a normal number here)
+__device__ __forceinline__ double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  double e = fma(-q, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-q, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Register-resident layout of an a x a matrix (a <= kTriLdsMax) over the
+// 1024 threads of a workgroup: thread t holds column c = t mod a, rows
+// [b rb, b rb + rb) with b = t / a < nb, nb = min(16, 1024 / a) row blocks.
+constexpr int kRegRows = 20;  // rb <= 20 for a <= 136
+
+struct RegLayout {
+  int nb, rb, c, b, r0, nrow;
+  bool act;
+  __device__ RegLayout(int a, int t) {
+    nb = min(16, kTriThreads / a);
+    rb = (a + nb - 1) / nb;
+    c = t % a;
+    b = t / a;
+    act = b < nb;
+    r0 = b * rb;
+    nrow = act ? max(0, min(rb, a - r0)) : 0;
+  }
+};
+
+// SplitMix64 finaliser (Steele, Lea, Flood 2014) mapped to [-1, 1)
+__device__ inline double unit_rand(unsigned long long key) {
+  key += 0x9e3779b97f4a7c15ULL;
+  key = (key ^ (key >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  key = (key ^ (key >> 27)) * 0x94d049bb133111ebULL;
+  key ^= key >> 31;
+  return (double)(key >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// Householder tridiagonalisation.  Step j maps column j below the diagonal
+// to alpha e_1 with H_j = I - tau_j v_j v_j^T (v_j stored in column j of R,
+// rows j+1..a-1) and updates the trailing block as
+// S <- S - v w^T - w v^T, w = p - (tau/2)(p.v) v, p = tau S v.  This
+// version (a > kTriLdsMax) keeps S in global memory; k_tridiag_reg below
+// holds it in registers.
+__global__ __launch_bounds__(kTriThreads) void k_tridiag(const double* __restrict__ G, int a,
+                                                         double* Sg, double* __restrict__ R,
+                                                         double* __restrict__ tau_out,
+                                                         double* __restrict__ d,
+                                                         double* __restrict__ e,
+                                                         double* __restrict__ misc) {
+  extern __shared__ double sm[];
+  constexpr int ng = 4;
+  double* S = Sg;
+  double* v = sm;
+  double* w = v + a;
+  double* part = w + a;  // ng x a partial products
+  __shared__ double red[kTriThreads / 64];
+  __shared__ double scale_s, tau_s;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int aa = a * a;
+
+  double mx = 0.0;
+  for (int i = tid; i < aa; i += kTriThreads) mx = fmax(mx, fabs(G[i]));
+  mx = wave_max(mx);
+  if (lane == 0) red[wv] = mx;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < kTriThreads / 64; ++i) m = fmax(m, red[i]);
+    scale_s = (m > 0.0 && m <= DBL_MAX) ? ldexp(1.0, -ilogb(m)) : 1.0;
+    misc[0] = scale_s;
+  }
+  __syncthreads();
+  const double sc = scale_s;
+  for (int i = tid; i < aa; i += kTriThreads) S[i] = G[i] * sc;
+  __syncthreads();
+
+  for (int j = 0; j + 2 < a; ++j) {
+    const int m = a - 1 - j;  // trailing order, >= 2
+    const int o = j + 1;      // first trailing index
+    const double* xj = S + (size_t)j * a + o;
+    if (wv == 0) {
+      double xx = 0.0;
+      for (int r = 1 + lane; r < m; r += 64) xx += xj[r] * xj[r];
+      xx = wave_sum(xx);
+      const double x0 = xj[0];
+      double alpha, tau, v0;
+      if (xx == 0.0) {
+        alpha = x0;
+        tau = 0.0;
+        v0 = 0.0;
+      } else {
+        const double nx = sqrt(x0 * x0 + xx);
+        alpha = x0 >= 0.0 ? -nx : nx;
+        v0 = x0 - alpha;
+        tau = 2.0 / (v0 * v0 + xx);
+      }
+      for (int r = lane; r < m; r += 64) {
+        const double vr = tau == 0.0 ? 0.0 : (r == 0 ? v0 : xj[r]);
+        v[r] = vr;
+        R[(size_t)j * a + o + r] = vr;
+      }
+      if (lane == 0) {
+        tau_s = tau;
+        tau_out[j] = tau;
+        e[j] = alpha;
+        d[j] = S[(size_t)j * a + j];
+      }
+    }
+    __syncthreads();
+    const double tau = tau_s;
+    if (tau != 0.0) {
+      for (int idx = tid; idx < m * ng; idx += kTriThreads) {
+        const int r = idx % m, g = idx / m;
+        const double* col = S + (size_t)o * a + o + r;
+        double acc = 0.0;
+        for (int c = g; c < m; c += ng) acc += col[(size_t)c * a] * v[c];
+        part[g * a + r] = acc;
+      }
+      __syncthreads();
+      if (wv == 0) {
+        double pv = 0.0;
+        for (int r = lane; r < m; r += 64) {
+          double p = 0.0;
+          for (int g = 0; g < ng; ++g) p += part[g * a + r];
+          p *= tau;
+          w[r] = p;
+          pv += p * v[r];
+        }
+        pv = wave_sum(pv);
+        const double K = 0.5 * tau * pv;
+        for (int r = lane; r < m; r += 64) w[r] -= K * v[r];
+      }
+      __syncthreads();
+      for (int idx = tid; idx < m * m; idx += kTriThreads) {
+        const int r = idx % m, c = idx / m;
+        S[(size_t)(o + c) * a + o + r] -= v[r] * w[c] + w[r] * v[c];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (a >= 2) {
+      d[a - 2] = S[(size_t)(a - 2) * a + a - 2];
+      e[a - 2] = S[(size_t)(a - 2) * a + a - 1];
+    }
+    d[a - 1] = S[(size_t)(a - 1) * a + a - 1];
+    e[a - 1] = 0.0;
+  }
+}
+
+// The same reduction for a <= kTriLdsMax with the matrix in registers
+// (RegLayout; S symmetric, so a thread's column slice is also a row slice).
+// Per step: partial norms of column j -> alpha, tau, v (every thread derives
+// them from the same partials in the same order) -> partial column products
+// of the trailing block with v -> p, K = tau/2 p.v, w -> rank-2 update.
+// v and w live in LDS, zero outside the trailing rows (and in the padding up
+// to nb rb); register slots k >= nrow stay zero.
+constexpr int kPadRows = kTriLdsMax + kRegRows;
+
+__global__ __launch_bounds__(kTriThreads) void k_tridiag_reg(const double* __restrict__ G, int a,
+                                                             double* __restrict__ R,
+                                                             double* __restrict__ tau_out,
+                                                             double* __restrict__ d,
+                                                             double* __restrict__ e,
+                                                             double* __restrict__ misc) {
+  __shared__ double vbuf[kPadRows], wbuf[kPadRows];
+  __shared__ double pd[16 * kTriLdsMax];
+  __shared__ double red[kTriThreads / 64], npart[16];
+  __shared__ double sc_s, x0_s, d_s;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const RegLayout L(a, t);
+  const int c = L.c, b = L.b, r0 = L.r0, nrow = L.nrow, nb = L.nb;
+  const bool act = L.act;
+
+  for (int i = t; i < kPadRows; i += kTriThreads) {
+    vbuf[i] = 0.0;
+    wbuf[i] = 0.0;
+  }
+  double mx = 0.0;
+  for (int i = t; i < a * a; i += kTriThreads) mx = fmax(mx, fabs(G[i]));
+  mx = wave_max(mx);
+  if (lane == 0) red[wv] = mx;
+  __syncthreads();
+  if (t == 0) {
+    double m = 0.0;
+    for (int i = 0; i < kTriThreads / 64; ++i) m = fmax(m, red[i]);
+    sc_s = (m > 0.0 && m <= DBL_MAX) ? ldexp(1.0, -ilogb(m)) : 1.0;
+    misc[0] = sc_s;
+  }
+  __syncthreads();
+  const double sc = sc_s;
+  double x[kRegRows];
+#pragma unroll
+  for (int k = 0; k < kRegRows; ++k) x[k] = k < nrow ? G[(size_t)c * a + r0 + k] * sc : 0.0;
+  const double* vrow = vbuf + (act ? r0 : 0);
+  const double* wrow = wbuf + (act ? r0 : 0);
+
+  for (int j = 0; j + 2 < a; ++j) {
+    const bool own = act && c == j;
+    if (own) {
+      double sq = 0.0;
+#pragma unroll
+      for (int k = 0; k < kRegRows; ++k) {
+        const int r = r0 + k;
+        if (r > j + 1) sq += x[k] * x[k];
+        if (k < nrow && r == j + 1) x0_s = x[k];
+        if (k < nrow && r == j) d_s = x[k];
+      }
+      npart[b] = sq;
+    }
+    __syncthreads();
+    double xx = 0.0;
+    for (int bb = 0; bb < nb; ++bb) xx += npart[bb];
+    const double x0 = x0_s;
+    double alpha, tau, v0;
+    if (xx == 0.0) {
+      alpha = x0;
+      tau = 0.0;
+      v0 = 0.0;
+    } else {
+      const double nx = sqrt(x0 * x0 + xx);
+      alpha = x0 >= 0.0 ? -nx : nx;
+      v0 = x0 - alpha;
+      tau = 2.0 / (v0 * v0 + xx);
+    }
+    if (own) {
+#pragma unroll
+      for (int k = 0; k < kRegRows; ++k) {
+        const int r = r0 + k;
+        if (k < nrow) {
+          const double vr = (tau == 0.0 || r <= j) ? 0.0 : (r == j + 1 ? v0 : x[k]);
+          vbuf[r] = vr;
+          if (r > j) R[(size_t)j * a + r] = vr;
+        }
+      }
+    }
+    if (t == 0) {
+      tau_out[j] = tau;
+      e[j] = alpha;
+      d[j] = d_s;
+    }
+    __syncthreads();
+    if (tau != 0.0) {
+      const bool live = act && c > j;
+      if (live) {
+        double sp = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRegRows; ++k) sp += x[k] * vrow[k];
+        pd[b * kTriLdsMax + c] = sp;
+      }
+      __syncthreads();
+      double pc = 0.0, vc = 0.0;
+      if (live) {
+        for (int bb = 0; bb < nb; ++bb) pc += pd[bb * kTriLdsMax + c];
+        pc *= tau;
+        vc = vbuf[c];
+      }
+      double contrib = (live && b == 0) ? pc * vc : 0.0;
+      contrib = wave_sum(contrib);
+      if (lane == 0) red[wv] = contrib;
+      __syncthreads();
+      double K = 0.0;
+      for (int i = 0; i < kTriThreads / 64; ++i) K += red[i];
+      K *= 0.5 * tau;
+      const double wc = pc - K * vc;
+      if (act && b == 0) wbuf[c] = live ? wc : 0.0;
+      __syncthreads();
+      if (live) {
+#pragma unroll
+        for (int k = 0; k < kRegRows; ++k)
+          if (k < nrow) x[k] -= vrow[k] * wc + wrow[k] * vc;
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < kRegRows; ++k) {
+      const int r = r0 + k;
+      if (k < nrow) {
+        if (c == a - 2 && r == a - 2) d[a - 2] = x[k];
+        if (c == a - 2 && r == a - 1) e[a - 2] = x[k];
+        if (c == a - 1 && r == a - 1) d[a - 1] = x[k];
+      }
+    }
+  }
+  if (t == 0) e[a - 1] = 0.0;
+}
+
+// Number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots);
+// pivots smaller than pivmin in magnitude are replaced by -pivmin.
+__device__ inline int sturm_count(const double* dd, const double* e2, int a, double x, double pivmin) {
+  double q = dd[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int c = q < 0.0;
+  for (int i = 1; i < a; ++i) {
+    q = (dd[i] - x) - e2[i - 1] * recip(q);
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+// Eigenvalue k (k-th smallest) of T: the interval [L, H] with
+// count(L) <= k < count(H) is cut at 63 interior points per step (one per
+// lane) and replaced by the sub-interval where the count passes k.
+__global__ __launch_bounds__(64 * kBisWaves) void k_bisect(int a, const double* __restrict__ d,
+                                                           const double* __restrict__ e,
+                                                           const double* __restrict__ misc,
+                                                           double* __restrict__ lam,
+                                                           double* __restrict__ w_out) {
+  extern __shared__ double bs[];
+  double* dd = bs;
+  double* e2 = bs + a;
+  __shared__ double rlo[kBisWaves], rhi[kBisWaves], re2[kBisWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double lo = INFINITY, hi = -INFINITY, em = 0.0;
+  for (int i = tid; i < a; i += 64 * kBisWaves) {
+    const double di = d[i];
+    const double el = i > 0 ? fabs(e[i - 1]) : 0.0;
+    const double er = i + 1 < a ? fabs(e[i]) : 0.0;
+    dd[i] = di;
+    e2[i] = er * er;
+    lo = fmin(lo, di - el - er);
+    hi = fmax(hi, di + el + er);
+    em = fmax(em, er * er);
+  }
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  em = wave_max(em);
+  if (lane == 0) {
+    rlo[wv] = lo;
+    rhi[wv] = hi;
+    re2[wv] = em;
+  }
+  __syncthreads();
+  lo = rlo[0];
+  hi = rhi[0];
+  em = re2[0];
+  for (int i = 1; i < kBisWaves; ++i) {
+    lo = fmin(lo, rlo[i]);
+    hi = fmax(hi, rhi[i]);
+    em = fmax(em, re2[i]);
+  }
+  const int k = blockIdx.x * kBisWaves + wv;
+  if (k >= a) return;  // no barrier follows
+  const double tn = fmax(fabs(lo), fabs(hi));
+  const double pivmin = DBL_MIN * fmax(1.0, em);
+  const double margin = 2.0 * DBL_EPSILON * tn * a + 2.0 * pivmin;
+  double L = lo - margin, H = hi + margin;
+  // below 1e-3 u ||T|| the eigenvalues of the rounded Gram matrix carry no
+  // information; bisecting further only costs time
+  const double abstol = 1e-3 * DBL_EPSILON * tn;
+  for (int it = 0; it < 24; ++it) {
+    const double x = L + (H - L) * (double)(lane + 1) * (1.0 / 64.0);
+    const bool above = lane < 63 && sturm_count(dd, e2, a, x, pivmin) > k;
+    const unsigned long long mask = __ballot(above);
+    const int first = mask ? __ffsll((long long)mask) - 1 : 63;
+    const double xf = __shfl(x, first, 64);
+    const double xp = __shfl(x, first > 0 ? first - 1 : 0, 64);
+    const double nH = first == 63 ? H : xf;
+    const double nL = first == 0 ? L : xp;
+    if (!(nL > L || nH < H)) break;
+    L = nL;
+    H = nH;
+    if (H - L <= fmax(2.0 * DBL_EPSILON * fmax(fabs(L), fabs(H)), abstol)) break;
+  }
+  if (lane == 0) {
+    const double l = 0.5 * (L + H);
+    lam[a - 1 - k] = l;
+    w_out[a - 1 - k] = l / misc[0];
+  }
+}
+
+// Inverse iteration for one eigenvalue l of T (one thread): T - l I = P L U
+// with partial pivoting (multiplier, pivot flag and the three rows of U per
+// row), then two solves, the first from a pseudo-random start, the second
+// from its normalised result.  Pivots smaller than u ||T|| are replaced by
+// +-u ||T|| and right-hand sides have norm <= sqrt(a), so a row of the back
+// substitution stays finite; the column is rescaled whenever a value exceeds
+// 1e100.  Row r of the work arrays and of the vector x is at [r * stride].
+__device__ void invit_one(int a, const double* dd, const double* ee, double tn, double l,
+                          unsigned long long seed, double* Mu, double* Ui, double* U1, double* U2,
+                          double* Pv, double* x, int stride) {
+  // ||T|| >= max |G_ij| >= 1 after the scaling unless G = 0, where any
+  // nonzero floor gives the same direction
+  const double pert = tn > 0.0 ? DBL_EPSILON * tn : 1.0;
+  auto floor_pivot = [pert](double u) { return fabs(u) < pert ? (u >= 0.0 ? pert : -pert) : u; };
+  // factorisation, eliminating the random right-hand side on the fly; Ui
+  // holds the reciprocals of the pivots
+  double cd = dd[0] - l, cu = a > 1 ? ee[0] : 0.0, cb = unit_rand(seed);
+  for (int r = 0; r + 1 < a; ++r) {
+    const double sub = ee[r];
+    const double nd = dd[r + 1] - l;
+    const double nu = r + 2 < a ? ee[r + 1] : 0.0;
+    const double nb = unit_rand(seed + r + 1);
+    double ui, u1, u2, mlt, pv, br;
+    if (fabs(cd) >= fabs(sub)) {
+      ui = 1.0 / floor_pivot(cd);
+      mlt = sub * ui;
+      u1 = cu;
+      u2 = 0.0;
+      pv = 0.0;
+      br = cb;
+      cb = nb - mlt * cb;
+      cd = nd - mlt * cu;
+      cu = nu;
+    } else {
+      ui = 1.0 / sub;
+      mlt = cd * ui;
+      u1 = nd;
+      u2 = nu;
+      pv = 1.0;
+      br = nb;
+      cb = cb - mlt * nb;
+      cd = cu - mlt * nd;
+      cu = -mlt * nu;
+    }
+    const int o = r * stride;
+    Mu[o] = mlt;
+    Ui[o] = ui;
+    U1[o] = u1;
+    U2[o] = u2;
+    Pv[o] = pv;
+    x[o] = br;
+  }
+  Ui[(a - 1) * stride] = 1.0 / floor_pivot(cd);
+  x[(a - 1) * stride] = cb;
+
+  for (int step = 0; step < 2; ++step) {
+    if (step == 1) {
+      double cbf = x[0];
+      for (int r = 0; r + 1 < a; ++r) {
+        const int o = r * stride;
+        const double nb = x[o + stride];
+        const double mlt = Mu[o];
+        double br;
+        if (Pv[o] != 0.0) {
+          br = nb;
+          cbf = cbf - mlt * nb;
+        } else {
+          br = cbf;
+          cbf = nb - mlt * cbf;
+        }
+        x[o] = br;
+      }
+      x[(a - 1) * stride] = cbf;
+    }
+    double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+    for (int r = a - 1; r >= 0; --r) {
+      const int o = r * stride;
+      const double u1 = r + 1 < a ? U1[o] : 0.0;
+      const double u2 = r + 2 < a ? U2[o] : 0.0;
+      double xr = (x[o] - u1 * x1 - u2 * x2) * Ui[o];
+      while (fabs(xr) > 1e100) {
+        // growth through several floored pivots: the system is linear, so
+        // rescale the whole column (solved rows and pending right-hand side)
+        for (int q = 0; q < a; ++q) x[q * stride] *= 1e-100;
+        xr *= 1e-100;
+        x1 *= 1e-100;
+        x2 *= 1e-100;
+        nrm *= 1e-200;
+      }
+      x[o] = xr;
+      nrm += xr * xr;
+      x2 = x1;
+      x1 = xr;
+    }
+    if (step == 0) {
+      const double sn = nrm > 0.0 ? 1.0 / sqrt(nrm) : 1.0;
+      for (int r = 0; r < a; ++r) x[r * stride] *= sn;
+    }
+  }
+}
+
+__device__ inline double tri_norm(int a, const double* dd, const double* ee) {
+  double t = 0.0;
+  for (int r = threadIdx.x & 63; r < a; r += 64)
+    t = fmax(t, fabs(dd[r]) + fabs(ee[r]) + (r > 0 ? fabs(ee[r - 1]) : 0.0));
+  return wave_max(t);
+}
+
+__device__ inline unsigned long long invit_seed(int i) {
+  return 0x5851f42d4c957f2dULL * (unsigned long long)(i + 1);
+}
+
+// a <= kTriLdsMax: kInvLds threads (eigenvalues) per workgroup, work arrays
+// and vectors in LDS as [row][thread]; X (global, [row][eigenvalue])
+// receives the unnormalised vectors.
+constexpr int kInvLds = 16;
+
+__global__ __launch_bounds__(64) void k_invit_lds(int a, const double* __restrict__ d,
+                                                  const double* __restrict__ e,
+                                                  const double* __restrict__ lam,
+                                                  double* __restrict__ X) {
+  __shared__ double dd[kTriLdsMax], ee[kTriLdsMax];
+  __shared__ double wk[6 * kTriLdsMax * kInvLds];
+  __shared__ double tnr;
+  for (int r = threadIdx.x; r < a; r += 64) {
+    dd[r] = d[r];
+    ee[r] = e[r];
+  }
+  __syncthreads();
+  const double tn = tri_norm(a, dd, ee);
+  if (threadIdx.x == 0) tnr = tn;
+  __syncthreads();
+  const int tl = threadIdx.x;
+  const int i = blockIdx.x * kInvLds + tl;
+  if (tl >= kInvLds || i >= a) return;  // no barrier follows
+  const int plane = kTriLdsMax * kInvLds;
+  double* base = wk + tl;
+  invit_one(a, dd, ee, tnr, lam[i], invit_seed(i), base, base + plane, base + 2 * plane,
+            base + 3 * plane, base + 4 * plane, base + 5 * plane, kInvLds);
+  for (int r = 0; r < a; ++r) X[(size_t)r * a + i] = base[5 * plane + r * kInvLds];
+}
+
+// a > kTriLdsMax: one thread per eigenvalue, work arrays in global memory
+// ([row][eigenvalue], contiguous across a wavefront).
+__global__ __launch_bounds__(kInvThreads) void k_invit(int a, const double* __restrict__ d,
+                                                       const double* __restrict__ e,
+                                                       const double* __restrict__ lam,
+                                                       double* __restrict__ LU,
+                                                       double* __restrict__ X) {
+  extern __shared__ double ts[];
+  double* dd = ts;
+  double* ee = ts + a;
+  __shared__ double tnr;
+  for (int r = threadIdx.x; r < a; r += kInvThreads) {
+    dd[r] = d[r];
+    ee[r] = e[r];
+  }
+  __syncthreads();
+  const double tn = tri_norm(a, dd, ee);
+  if (threadIdx.x == 0) tnr = tn;
+  __syncthreads();
+  const int i = blockIdx.x * kInvThreads + threadIdx.x;
+  if (i >= a) return;  // no barrier follows
+  const size_t aa = (size_t)a * a;
+  invit_one(a, dd, ee, tnr, lam[i], invit_seed(i), LU + i, LU + aa + i, LU + 2 * aa + i,
+            LU + 3 * aa + i, LU + 4 * aa + i, X + i, a);
+}
+
+// Two passes of modified Gram-Schmidt over the columns of X in eigenvalue
+// order (columns kept unnormalised during a pass, their squared norms in
+// nrm), each pass followed by normalisation.  Xin is [row][column];
+// Xo receives the orthonormal columns column-major.  Global-memory version
+// for a > kTriLdsMax (Xg: a x a scratch).
+__global__ __launch_bounds__(kTriThreads) void k_mgs(int a, const double* __restrict__ Xin,
+                                                     double* __restrict__ Xo, double* Xg) {
+  extern __shared__ double ms[];
+  double* Q = Xg;
+  double* nrm = ms;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int nw = kTriThreads / 64;
+  const int aa = a * a;
+  for (int idx = tid; idx < aa; idx += kTriThreads) {
+    const int r = idx % a, c = idx / a;
+    Q[idx] = Xin[(size_t)r * a + c];
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    if (wv == 0) {
+      double s = 0.0;
+      for (int r = lane; r < a; r += 64) s += Q[r] * Q[r];
+      s = wave_sum(s);
+      if (lane == 0) nrm[0] = s;
+    }
+    __syncthreads();
+    for (int j = 0; j + 1 < a; ++j) {
+      const double nj = nrm[j];
+      const double* qj = Q + (size_t)j * a;
+      for (int c = j + 1 + wv; c < a; c += nw) {
+        double* qc = Q + (size_t)c * a;
+        double dp = 0.0;
+        for (int r = lane; r < a; r += 64) dp += qj[r] * qc[r];
+        dp = wave_sum(dp);
+        const double coef = nj > 0.0 ? dp / nj : 0.0;
+        double s = 0.0;
+        for (int r = lane; r < a; r += 64) {
+          const double y = qc[r] - coef * qj[r];
+          qc[r] = y;
+          s += y * y;
+        }
+        if (c == j + 1) {
+          s = wave_sum(s);
+          if (lane == 0) nrm[c] = s;
+        }
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < aa; idx += kTriThreads) {
+      const double n2 = nrm[idx / a];
+      if (n2 > 0.0) Q[idx] *= 1.0 / sqrt(n2);
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < aa; idx += kTriThreads) Xo[idx] = Q[idx];
+}
+
+// Modified Gram-Schmidt for a <= kTriLdsMax with the columns in registers
+// (RegLayout).  Step j: the owners of column j publish it and its squared
+// norm (block partials); every thread forms its partial product with its
+// column, the partials of a column are summed in block order, and the
+// column is updated.  A second pass runs only when some pair of columns of
+// the first pass had |cos| > 1e-3 (one pass of Gram-Schmidt then already
+// leaves them orthogonal to rounding level).  Xin is [row][column], Xo
+// column-major.
+__global__ __launch_bounds__(kTriThreads) void k_mgs_reg(int a, const double* __restrict__ Xin,
+                                                         double* __restrict__ Xo) {
+  __shared__ double qbuf[kTriLdsMax];
+  __shared__ double pd[16 * kTriLdsMax];
+  __shared__ double np[16];
+  __shared__ double red[kTriThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const RegLayout L(a, t);
+  const int c = L.c, b = L.b, r0 = L.r0, nrow = L.nrow, nb = L.nb;
+  const bool act = L.act;
+  double x[kRegRows];
+#pragma unroll
+  for (int k = 0; k < kRegRows; ++k) x[k] = k < nrow ? Xin[(size_t)(r0 + k) * a + c] : 0.0;
+  for (int pass = 0; pass < 2; ++pass) {
+    double cmax = 0.0;  // largest |cos| between column c and an earlier column
+    if (act && c == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < kRegRows; ++k) {
+        if (k < nrow) qbuf[r0 + k] = x[k];
+        s += x[k] * x[k];
+      }
+      np[b] = s;
+    }
+    __syncthreads();
+    double mynorm = 0.0;
+    for (int j = 0; j + 1 < a; ++j) {
+      double nj = 0.0;
+      for (int bb = 0; bb < nb; ++bb) nj += np[bb];
+      if (c == j) mynorm = nj;
+      const bool live = act && c > j;
+      double q[kRegRows];
+#pragma unroll
+      for (int k = 0; k < kRegRows; ++k) q[k] = (live && k < nrow) ? qbuf[r0 + k] : 0.0;
+      if (live) {
+        double sp = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRegRows; ++k) sp += q[k] * x[k];
+        pd[b * kTriLdsMax + c] = sp;
+      }
+      __syncthreads();
+      if (live) {
+        double dot = 0.0;
+        for (int bb = 0; bb < nb; ++bb) dot += pd[bb * kTriLdsMax + c];
+        const double coef = nj > 0.0 ? dot / nj : 0.0;
+        double s = 0.0, before = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRegRows; ++k) {
+          before += x[k] * x[k];
+          x[k] -= coef * q[k];
+          s += x[k] * x[k];
+        }
+        if (pass == 0 && nj > 0.0 && before > 0.0) cmax = fmax(cmax, fabs(dot) * rsqrt(nj) * rsqrt(before));
+        if (c == j + 1) {
+#pragma unroll
+          for (int k = 0; k < kRegRows; ++k)
+            if (k < nrow) qbuf[r0 + k] = x[k];
+          np[b] = s;
+        }
+      }
+      __syncthreads();
+    }
+    double nl = 0.0;
+    for (int bb = 0; bb < nb; ++bb) nl += np[bb];
+    if (c == a - 1) mynorm = nl;
+    const double sc = mynorm > 0.0 ? 1.0 / sqrt(mynorm) : 0.0;
+#pragma unroll
+    for (int k = 0; k < kRegRows; ++k) x[k] *= sc;
+    // decide on the second pass (the same decision in every thread)
+    cmax = wave_max(cmax);
+    if (lane == 0) red[wv] = cmax;
+    __syncthreads();
+    double cm = 0.0;
+    for (int i = 0; i < kTriThreads / 64; ++i) cm = fmax(cm, red[i]);
+    if (pass == 0 && cm <= 1e-3) break;
+    __syncthreads();
+  }
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < kRegRows; ++k)
+      if (k < nrow) Xo[(size_t)c * a + r0 + k] = x[k];
+  }
+}
+
+// V = H_0 H_1 ... H_{a-3} X, one wavefront per column of X; the reflectors
+// are staged in LDS when they fit.
+__global__ __launch_bounds__(64 * kBackWaves) void k_backtransform(int a, const double* __restrict__ Rg,
+                                                                   const double* __restrict__ tau_g,
+                                                                   const double* __restrict__ X,
+                                                                   double* __restrict__ V) {
+  extern __shared__ double bt[];
+  const bool in_lds = a <= kTriLdsMax;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int aa = a * a;
+  double* col = in_lds ? bt + aa + a : bt;
+  if (in_lds) {
+    for (int idx = tid; idx < aa; idx += 64 * kBackWaves) bt[idx] = Rg[idx];
+    for (int idx = tid; idx < a; idx += 64 * kBackWaves) bt[aa + idx] = tau_g[idx];
+    __syncthreads();
+  }
+  const double* Rs = in_lds ? bt : Rg;
+  const double* ts = in_lds ? bt + aa : tau_g;
+  const int c = blockIdx.x * kBackWaves + wv;
+  if (c >= a) return;  // no barrier follows
+  double* x = col + (size_t)wv * a;
+  for (int r = lane; r < a; r += 64) x[r] = X[(size_t)c * a + r];
+  for (int j = a - 3; j >= 0; --j) {
+    const double t = ts[j];
+    if (t == 0.0) continue;
+    const double* vj = Rs + (size_t)j * a;
+    double dp = 0.0;
+    for (int r = j + 1 + lane; r < a; r += 64) dp += vj[r] * x[r];
+    dp = wave_sum(dp) * t;
+    for (int r = j + 1 + lane; r < a; r += 64) x[r] -= dp * vj[r];
+  }
+  for (int r = lane; r < a; r += 64) V[(size_t)c * a + r] = x[r];
+}
+
+}  // namespace
+
+size_t sym_eig_work(int a) { return (size_t)10 * a * a + 8 * (size_t)a + 16; }
+
+void sym_eig(hipStream_t s, const double* G, int a, double* V, double* w, double* work) {
+  if (a <= 0) return;
+  const size_t aa = (size_t)a * a;
+  double* R = work;
+  double* tau = R + aa;
+  double* d = tau + a;
+  double* e = d + a;
+  double* lam = e + a;
+  double* misc = lam + a;
+  double* S = misc + 16;
+  double* LU = S + aa;
+  double* X = LU + 5 * aa;
+  double* Xo = X + aa;
+  if (a <= kTriLdsMax) {
+    hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(kTriThreads), 0, s, G, a, R, tau, d, e, misc);
+  } else {
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kTriThreads), sizeof(double) * 6 * a, s, G, a, S, R, tau, d,
+                       e, misc);
+  }
+  check("sym_eig tridiag");
+  hipLaunchKernelGGL(k_bisect, dim3((a + kBisWaves - 1) / kBisWaves), dim3(64 * kBisWaves),
+                     sizeof(double) * 2 * a, s, a, d, e, misc, lam, w);
+  check("sym_eig bisect");
+  if (a <= kTriLdsMax) {
+    hipLaunchKernelGGL(k_invit_lds, dim3((a + kInvLds - 1) / kInvLds), dim3(64), 0, s, a, d, e, lam, X);
+  } else {
+    hipLaunchKernelGGL(k_invit, dim3((a + kInvThreads - 1) / kInvThreads), dim3(kInvThreads),
+                       sizeof(double) * 2 * a, s, a, d, e, lam, LU, X);
+  }
+  check("sym_eig invit");
+  if (a <= kTriLdsMax) {
+    hipLaunchKernelGGL(k_mgs_reg, dim3(1), dim3(kTriThreads), 0, s, a, X, Xo);
+  } else {
+    hipLaunchKernelGGL(k_mgs, dim3(1), dim3(kTriThreads), sizeof(double) * a, s, a, X, Xo, S);
+  }
+  check("sym_eig mgs");
+  const size_t bt_lds = sizeof(double) * ((a <= kTriLdsMax ? aa + a : 0) + (size_t)kBackWaves * a);
+  hipLaunchKernelGGL(k_backtransform, dim3((a + kBackWaves - 1) / kBackWaves), dim3(64 * kBackWaves),
+                     bt_lds, s, a, R, tau, Xo, V);
+  check("sym_eig backtransform");
+}
+
+}  // namespace gpu
+}  // namespace tk

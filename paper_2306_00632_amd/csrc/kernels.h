@@ -33,17 +33,14 @@ struct QrJob {
 };
 void householder_qr(hipStream_t s, const QrJob* jobs, int njobs);
 
-// Symmetric eigendecomposition G = V diag(w) V^T of an a x a matrix by
-// parallel cyclic Jacobi in one workgroup (LDS-resident for a <= 140) whose
-// rotations are recorded in `rot` (jacobi_rot_capacity(a) entries) and then
-// replayed on the identity by many workgroups to form V.  `work` must hold
-// (a+1)^2 doubles when a > 140.  rounds[0] = rounds executed, rounds[1] =
-// sweeps (device ints).  Couplings too small to move 1e-6 of the
-// truncation budget eps^2 norm2 / 3 (norm2: device scalar, or the trace of G
-// when null) between the kept and discarded directions are not rotated away.
-size_t jacobi_rot_capacity(int a);
-void jacobi_eig(hipStream_t s, double* G, int a, double* V, double* w, double* work, double2* rot,
-                int* rounds, double eps, const double* norm2);
+// Symmetric eigendecomposition G = V diag(w) V^T of an a x a matrix
+// (a <= 2048): Householder tridiagonalisation, multisection for the
+// eigenvalues, inverse iteration, two Gram-Schmidt passes and the back
+// transformation, five launches on stream s.  V is column-major with the
+// eigenvectors in descending eigenvalue order, w descending.  `work` holds
+// sym_eig_work(a) doubles.  G is not modified.
+size_t sym_eig_work(int a);
+void sym_eig(hipStream_t s, const double* G, int a, double* V, double* w, double* work);
 
 // e[j] = sum_i P[i, j]^2 for the a columns of P (rows x a, ld rows)
 void column_energy(hipStream_t s, const double* P, int rows, int a, double* e);

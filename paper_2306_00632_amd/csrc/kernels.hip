@@ -312,200 +312,6 @@ void householder_qr(hipStream_t s, const QrJob* jobs, int njobs) {
 }
 
 // ---------------------------------------------------------------------------
-// Jacobi eigensolver
-// ---------------------------------------------------------------------------
-
-constexpr int kJacLdsMax = 140;
-constexpr int kJacThreads = 1024;
-constexpr int kJacMaxSweeps = 40;
-
-// round-robin pairing: in round r of a sweep over P (even) indices, slot t
-// pairs (p, q); every pair occurs once per sweep of P-1 rounds
-__device__ inline void jac_pair(int r, int t, int P, int& p, int& q) {
-  if (t == 0) { p = r % (P - 1); q = P - 1; }
-  else { p = (r + t) % (P - 1); q = (r - t + P - 1) % (P - 1); }
-  if (p > q) { const int x = p; p = q; q = x; }
-}
-
-// Cyclic Jacobi on S = G (a x a, padded to even P), one workgroup.  The
-// rotations are not applied to an eigenvector matrix here; they are written
-// to `rot` (one (c, s) per slot and round) and replayed by k_jacobi_vectors.
-// A rotation is skipped when
-//  * |a_pq| <= 1e-13 sqrt(|a_pp a_qq|) (relative accuracy criterion,
-//    tolerance about n u), or
-//  * |a_pq| is below the rounding noise of the Gram matrix itself,
-//    1e-15 max_i |a_ii| (couplings at that level carry no information, and
-//    rotating the resulting cluster of noise-level eigenvalues with large
-//    angles only scrambles the couplings that still need removing), or
-//  * a_pq^2 <= leak * max(|a_pp|, |a_qq|) with leak = 1e-6 budget / a: the
-//    energy that the coupling can move between the two directions is then
-//    a millionth of the truncation budget spread over all directions (the
-//    kept subspace tilts by at most ~1e-3 eps ||Z|| in total).  The
-//    caller measures the energy of every direction of the returned basis
-//    directly, so an unconverged coupling below this level can only cost a
-//    marginal rank, never accuracy.  budget = eps^2 norm2 / 3 with norm2 =
-//    *norm2 if given, else the trace of G.
-__global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict__ G, int a,
-                                                        double* __restrict__ w,
-                                                        double* __restrict__ work,
-                                                        double2* __restrict__ rot,
-                                                        int* __restrict__ rounds_out, double eps,
-                                                        const double* __restrict__ norm2) {
-  extern __shared__ double smem[];
-  const int P = (a + 1) & ~1;
-  const int H = P / 2;
-  const bool in_lds = P <= kJacLdsMax;
-  double* S = in_lds ? smem : work;
-  double2* csn = reinterpret_cast<double2*>(in_lds ? smem + P * P : smem);  // (c, s) per slot
-  int2* pq = reinterpret_cast<int2*>(csn + H);                              // (p, q) per slot
-  __shared__ int rotated;
-  __shared__ double dmax, leak;
-  for (int e = threadIdx.x; e < P * P; e += kJacThreads) {
-    const int i = e % P, j = e / P;
-    S[e] = (i < a && j < a) ? G[i + (long long)j * a] : 0.0;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double nz = 0.0;
-    if (norm2) nz = *norm2;
-    else for (int i = 0; i < a; ++i) nz += S[i + i * P];
-    leak = 1e-6 * (eps * eps * fmax(nz, 0.0) / 3.0) / a;
-  }
-  __syncthreads();
-  int sweep = 0;
-  int round_total = 0;
-  for (; sweep < kJacMaxSweeps; ++sweep) {
-    if (threadIdx.x == 0) {
-      rotated = 0;
-      double dm = 0.0;
-      for (int i = 0; i < a; ++i) dm = fmax(dm, fabs(S[i + i * P]));
-      dmax = dm;
-    }
-    __syncthreads();
-    const double floor_abs = 1e-15 * dmax;
-    for (int r = 0; r < P - 1; ++r, ++round_total) {
-      for (int t = threadIdx.x; t < H; t += kJacThreads) {
-        int p, q;
-        jac_pair(r, t, P, p, q);
-        double c = 1.0, s = 0.0;
-        const double apq = S[p + q * P];
-        if (q < a && apq != 0.0) {
-          const double app = S[p + p * P], aqq = S[q + q * P];
-          const double aa = fabs(apq);
-          if (!(aa <= 1e-13 * sqrt(fabs(app * aqq)) || aa <= floor_abs ||
-                aa * aa <= leak * fmax(fabs(app), fabs(aqq)))) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            s = tt * c;
-            rotated = 1;
-          }
-        }
-        csn[t] = make_double2(c, s);
-        pq[t] = make_int2(p, q);
-        rot[(long long)round_total * H + t] = make_double2(c, s);
-      }
-      __syncthreads();
-      // two-sided update of the 2x2 blocks (pair t1 rows, pair t2 columns)
-      for (int e = threadIdx.x; e < H * H; e += kJacThreads) {
-        const int t1 = e % H, t2 = e / H;
-        const double2 r1 = csn[t1], r2 = csn[t2];
-        const double c1 = r1.x, s1 = r1.y, c2 = r2.x, s2 = r2.y;
-        if (s1 == 0.0 && s2 == 0.0) continue;
-        const int2 i1 = pq[t1], i2 = pq[t2];
-        const int p1 = i1.x, q1 = i1.y, p2 = i2.x, q2 = i2.y;
-        const double xpp = S[p1 + p2 * P], xpq = S[p1 + q2 * P], xqp = S[q1 + p2 * P], xqq = S[q1 + q2 * P];
-        const double ypp = c1 * xpp - s1 * xqp, ypq = c1 * xpq - s1 * xqq;
-        const double yqp = s1 * xpp + c1 * xqp, yqq = s1 * xpq + c1 * xqq;
-        S[p1 + p2 * P] = c2 * ypp - s2 * ypq;
-        S[p1 + q2 * P] = s2 * ypp + c2 * ypq;
-        S[q1 + p2 * P] = c2 * yqp - s2 * yqq;
-        S[q1 + q2 * P] = s2 * yqp + c2 * yqq;
-      }
-      __syncthreads();
-    }
-    // every thread reads the flag before thread 0 may reset it
-    const bool done = (rotated == 0);
-    __syncthreads();
-    if (done) { ++sweep; break; }
-  }
-  for (int i = threadIdx.x; i < a; i += kJacThreads) w[i] = S[i + i * P];
-  if (threadIdx.x == 0) {
-    rounds_out[0] = round_total;
-    rounds_out[1] = sweep;
-  }
-}
-
-// V = product of the recorded rotations applied to the identity.  Row i of
-// V J is row i of V times J, so rows are independent: every wavefront owns
-// one row (in LDS) and replays all rounds on it with its lanes taking the
-// pairs of a round; only the staging of rotation chunks needs a workgroup
-// barrier.  Within a wavefront, LDS accesses are performed in program order,
-// so a round sees the previous round's values once the wave has waited for
-// its own LDS operations.
-constexpr int kVWaves = 8;   // rows (wavefronts) per workgroup
-constexpr int kVChunk = 32;  // rounds of rotations staged in LDS at a time
-
-__global__ __launch_bounds__(64 * kVWaves) void k_jacobi_vectors(int a, const double2* __restrict__ rot,
-                                                                 const int* __restrict__ rounds,
-                                                                 double* __restrict__ V, int chunk) {
-  extern __shared__ double vr[];  // kVWaves x P rows of V, then chunk x H rotations
-  const int P = (a + 1) & ~1, H = P / 2;
-  double2* rc = reinterpret_cast<double2*>(vr + kVWaves * P);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int i = blockIdx.x * kVWaves + wv;  // row of V owned by this wavefront
-  double* row = vr + wv * P;
-  for (int j = lane; j < P; j += 64) row[j] = (i == j) ? 1.0 : 0.0;
-  const int nr = rounds[0];
-  for (int c0 = 0; c0 < nr; c0 += chunk) {
-    const int nc = min(chunk, nr - c0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < nc * H; e += 64 * kVWaves) rc[e] = rot[(long long)c0 * H + e];
-    __syncthreads();
-    for (int k = 0; k < nc; ++k) {
-      const int r = (c0 + k) % (P - 1);
-      for (int t = lane; t < H; t += 64) {
-        const double2 cs = rc[k * H + t];
-        if (cs.y == 0.0) continue;
-        int p, q;
-        jac_pair(r, t, P, p, q);
-        const double vp = row[p], vq = row[q];
-        row[p] = cs.x * vp - cs.y * vq;
-        row[q] = cs.y * vp + cs.x * vq;
-      }
-      // order this round's LDS writes before the next round's reads (same wave)
-      __builtin_amdgcn_s_waitcnt(0xc07f);
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  if (i < a)
-    for (int j = lane; j < a; j += 64) V[i + (long long)j * a] = row[j];
-}
-
-size_t jacobi_rot_capacity(int a) {
-  const int P = (a + 1) & ~1;
-  return (size_t)kJacMaxSweeps * (P - 1) * (P / 2);
-}
-
-void jacobi_eig(hipStream_t s, double* G, int a, double* V, double* w, double* work, double2* rot,
-                int* rounds, double eps, const double* norm2) {
-  if (a <= 0) return;
-  const int P = (a + 1) & ~1;
-  size_t lds;
-  if (P <= kJacLdsMax) lds = sizeof(double) * P * P + sizeof(double2) * (P / 2) + sizeof(int2) * (P / 2);
-  else lds = sizeof(double2) * (P / 2) + sizeof(int2) * (P / 2);
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(kJacThreads), lds, s, G, a, w, work, rot, rounds, eps, norm2);
-  check_launch("jacobi_eig");
-  const int nb = (a + kVWaves - 1) / kVWaves;
-  // stage as many rounds as fit next to the rows in at most ~150 KB of LDS
-  const long long room = 150000LL - (long long)sizeof(double) * kVWaves * P;
-  const int chunk = (int)std::max<long long>(1, std::min<long long>(kVChunk, room / ((long long)sizeof(double2) * (P / 2))));
-  const size_t vlds = sizeof(double) * kVWaves * P + sizeof(double2) * chunk * (P / 2);
-  hipLaunchKernelGGL(k_jacobi_vectors, dim3(nb), dim3(64 * kVWaves), vlds, s, a, rot, rounds, V, chunk);
-  check_launch("jacobi_vectors");
-}
-
-// ---------------------------------------------------------------------------
 // rank selection
 // ---------------------------------------------------------------------------
 

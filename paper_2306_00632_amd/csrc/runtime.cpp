@@ -102,7 +102,7 @@ using BufP = std::shared_ptr<Buf>;
 
 namespace tk {
 // kernel families timed by the optional HIP-event instrumentation
-enum ProfKind { PK_BAND = 0, PK_GEMM, PK_QR, PK_JACOBI, PK_SELECT, PK_FD_FWD, PK_FD_BWD, PK_MISC, PK_N };
+enum ProfKind { PK_BAND = 0, PK_GEMM, PK_QR, PK_EIG, PK_SELECT, PK_FD_FWD, PK_FD_BWD, PK_MISC, PK_N };
 struct ProfRec {
   int kind;
   hipEvent_t a, b;
@@ -253,6 +253,14 @@ struct Prof {
     }
   }
 };
+
+// Dense flops of one symmetric eigendecomposition of order a: Householder
+// tridiagonalisation (4/3 a^3), two Gram-Schmidt passes (2 a^3 each) and the
+// back transformation (2 a^3); bisection and inverse iteration are O(a^2).
+static double eig_flops(int a) {
+  const double x = a;
+  return (4.0 / 3.0 + 4.0 + 2.0) * x * x * x;
+}
 
 static void gemm(tk_ctx* ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A, int lda,
                  const double* B, int ldb, double beta, double* C, int ldc) {
@@ -463,14 +471,10 @@ static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double*
     BufP G = alloc(ctx, (size_t)a * a);
     gemm(ctx, false, true, a, a, bc, 1.0, cur->p, a, cur->p, a, 0.0, G->p, a);
     BufP V = alloc(ctx, (size_t)a * a), w = alloc(ctx, (size_t)a);
-    BufP work;
-    if (((a + 1) & ~1) > 140) work = alloc(ctx, (size_t)(a + 1) * (a + 1));
-    BufP rot = alloc(ctx, 2 * gpu::jacobi_rot_capacity(a));
-    int* sweeps_dev = reinterpret_cast<int*>(ctx->sel->p) + 2100;
     {
-      Prof pr(ctx, PK_JACOBI, 8.0 * 2.0 * a * (double)a, 0.0);
-      gpu::jacobi_eig(ctx->stream, G->p, a, V->p, w->p, work ? work->p : nullptr,
-                      reinterpret_cast<double2*>(rot->p), sweeps_dev, eps, k == 0 ? nullptr : norm2);
+      BufP work = alloc(ctx, gpu::sym_eig_work(a));
+      Prof pr(ctx, PK_EIG, 8.0 * 2.0 * a * (double)a, eig_flops(a));
+      gpu::sym_eig(ctx->stream, G->p, a, V->p, w->p, work->p);
     }
     // P = A^T V (bc x a): columns are the mode-k coordinates in the eigenbasis
     BufP Pm = alloc(ctx, (size_t)bc * a);
@@ -482,20 +486,12 @@ static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double*
       gpu::column_energy(ctx->stream, Pm->p, bc, a, e->p);
       gpu::select_rank(ctx->stream, e->p, a, eps, norm2, k == 0 ? 1 : 0, sel, disc);
     }
-    int hsel = 0, hsweeps = 0;
+    int hsel = 0;
     double hdisc = 0.0;
     HIPCHK(hipMemcpyAsync(&hsel, sel, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    if (ctx->prof) HIPCHK(hipMemcpyAsync(&hsweeps, sweeps_dev + 1, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipMemcpyAsync(&hdisc, disc, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     if (k == 0) HIPCHK(hipMemcpyAsync(&P.norm2, norm2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     sync(ctx);
-    if (ctx->prof) {
-      // flops of the parallel Jacobi sweeps: (P-1) rounds of (P/2)^2 two-sided
-      // 2x2 block updates (24 flops) and their replay on the a x a
-      // eigenvector matrix (a*P/2 pairs of 6 flops)
-      const double Pd = double((a + 1) & ~1);
-      ctx->p_flops[PK_JACOBI] += hsweeps * (Pd - 1.0) * (6.0 * Pd * Pd + 3.0 * a * Pd);
-    }
     disc_total += hdisc;
     const int s = hsel;
     s_k[k] = s;
@@ -1171,27 +1167,12 @@ tk_status tk_prof_read(tk_ctx* ctx, int32_t kind, int64_t* launches, double* ms,
   });
 }
 
-tk_status tk_sym_eig(tk_ctx* ctx, const double* G, int32_t a, double eps, double* V, double* w,
-                     int32_t* sweeps) {
-  if (!ctx || !G || !V || !w || a < 1 || a > 2048 || !(eps >= 0.0)) return TK_EINVAL;
+tk_status tk_sym_eig(tk_ctx* ctx, const double* G, int32_t a, double* V, double* w) {
+  if (!ctx || !G || !V || !w || a < 1 || a > 2048) return TK_EINVAL;
   return guarded(ctx, [&]() {
-    BufP Gc = alloc(ctx, (size_t)a * a);
-    d2d(ctx, Gc->p, G, (size_t)a * a);
-    BufP work;
-    if (((a + 1) & ~1) > 140) work = alloc(ctx, (size_t)(a + 1) * (a + 1));
-    BufP rot = alloc(ctx, 2 * gpu::jacobi_rot_capacity(a));
-    int* rounds = reinterpret_cast<int*>(ctx->sel->p) + 2100;
-    {
-      Prof pr(ctx, PK_JACOBI, 8.0 * 2.0 * a * (double)a, 0.0);
-      gpu::jacobi_eig(ctx->stream, Gc->p, a, V, w, work ? work->p : nullptr,
-                      reinterpret_cast<double2*>(rot->p), rounds, eps, nullptr);
-    }
-    if (sweeps) {
-      int h = 0;
-      HIPCHK(hipMemcpyAsync(&h, rounds + 1, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-      sync(ctx);
-      *sweeps = h;
-    }
+    BufP work = alloc(ctx, gpu::sym_eig_work(a));
+    Prof pr(ctx, PK_EIG, 8.0 * 2.0 * a * (double)a, eig_flops(a));
+    gpu::sym_eig(ctx->stream, G, a, V, w, work->p);
     return TK_OK;
   });
 }

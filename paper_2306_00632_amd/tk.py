@@ -72,7 +72,7 @@ EXPORTS = {
     "fd_precond": (C.c_int32, [vp, vp, vp, C.POINTER(vp)]),
     "tucker_truncate": (C.c_int32, [vp, vp, C.c_double, C.POINTER(vp), dp]),
     "tk_tpcg_defaults": (None, [C.POINTER(TpcgParams)]),
-    "tk_sym_eig": (C.c_int32, [vp, vp, C.c_int32, C.c_double, vp, vp, i32p]),
+    "tk_sym_eig": (C.c_int32, [vp, vp, C.c_int32, vp, vp]),
     "tk_prof_enable": (C.c_int32, [vp, C.c_int32]),
     "tk_prof_reset": (C.c_int32, [vp]),
     "tk_prof_read": (C.c_int32, [vp, C.c_int32, i64p, dp, dp, dp]),
@@ -190,7 +190,7 @@ class Context:
     def sync(self):
         self.check(lib().tk_ctx_sync(self.h), "sync")
 
-    PROF_KINDS = ["band_apply", "dgemm", "householder_qr", "jacobi_eig", "select_rank",
+    PROF_KINDS = ["band_apply", "dgemm", "householder_qr", "sym_eig", "select_rank",
                   "fd_forward", "fd_backward", "misc"]
 
     def prof(self, on: bool = True, reset: bool = True):
@@ -399,12 +399,16 @@ def axpby(ctx, a, x: Tucker, b, y: Tucker) -> Tucker:
     return Tucker(ctx, h)
 
 
-def sym_eig(ctx, G_dev, a: int, V_dev, w_dev, eps: float = 0.0) -> int:
-    """Eigendecomposition of a device a x a matrix into device V, w; returns sweeps."""
-    sw = C.c_int32()
-    ctx.check(lib().tk_sym_eig(ctx.h, vp(G_dev.data_ptr()), a, eps, vp(V_dev.data_ptr()),
-                               vp(w_dev.data_ptr()), C.byref(sw)), "tk_sym_eig")
-    return sw.value
+def sym_eig(ctx, G_dev, a: int, V_dev, w_dev) -> None:
+    """Eigendecomposition G = V diag(w) V^T of a device a x a matrix
+    (column-major) into device V (a x a) and w (a), descending order.
+    Asynchronous on the context's stream."""
+    import torch
+    for t, n in ((G_dev, a * a), (V_dev, a * a), (w_dev, a)):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() < n:
+            raise ValueError("sym_eig needs contiguous float64 device tensors of the right size")
+    ctx.check(lib().tk_sym_eig(ctx.h, vp(G_dev.data_ptr()), a, vp(V_dev.data_ptr()),
+                               vp(w_dev.data_ptr())), "tk_sym_eig")
 
 
 def tpcg_params(**kw) -> TpcgParams:

@@ -7,12 +7,11 @@ Tolerances (FP64 throughout the GPU path):
 * truncation: the contract of eq. (rel_estimate), ||y - T(y)|| <= eps ||y||,
   exactly; the same ranks as the oracle's SVD-based ST-HOSVD; and agreement
   with the oracle's truncated tensor to 5e-3 eps (plus 1e-10): the GPU takes
-  the singular directions from a Jacobi-diagonalised Gram matrix whose
-  rotations stop once a remaining coupling could move less than 1e-6 of the
-  truncation budget eps^2 ||Z||^2 / 3 (a tilt of the kept subspace of order
-  1e-3 eps ||Z||), and it measures the discarded energy of its basis
-  directly, so its output differs from the exact ST-HOSVD only far inside
-  the truncation error;
+  the singular directions from the eigenvectors of the Gram matrix of each
+  unfolding (accurate to about u ||G|| / gap, i.e. squared conditioning
+  against the oracle's SVD of the unfolding) and measures the discarded
+  energy of its basis directly, so its output differs from the exact
+  ST-HOSVD only far inside the truncation error;
 * preconditioner: 1e-9 relative (the exponential-sum parameters of the
   library's and the oracle's independent Remez solvers agree to ~1e-11);
 * TPCG: relative solution error against the full-tensor reference
