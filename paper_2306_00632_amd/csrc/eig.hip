@@ -89,22 +89,25 @@ __device__ __forceinline__ double recip(double q) {
   return fma(r, e, r);
 }
 
-// Register-resident layout of an a x a matrix (a <= kTriLdsMax) over the
-// 1024 threads of a workgroup: thread t holds column c = t mod a, rows
-// [b rb, b rb + rb) with b = t / a < nb, nb = min(16, 1024 / a) row blocks.
-constexpr int kRegRows = 20;  // rb <= 20 for a <= 136
+// Register-resident layout of an a x a matrix (a <= kTriLdsMax) in one
+// workgroup of kRegThreads threads: thread t = b kTriLdsMax + c holds column
+// c (< a) for the kRegRows rows [b kRegRows, (b+1) kRegRows), b < kRegBlocks.
+// Rows at or beyond a are zero padding (in registers and in the LDS vectors
+// they meet), so the per-row loops have compile-time bounds and no tests.
+constexpr int kRegBlocks = 4;
+constexpr int kRegRows = 34;  // kRegBlocks * kRegRows >= kTriLdsMax
+constexpr int kRegThreads = 576;  // >= kRegBlocks * kTriLdsMax, whole wavefronts
+constexpr int kPadRows = kRegBlocks * kRegRows;
+static_assert(kPadRows >= kTriLdsMax, "row blocks must cover kTriLdsMax rows");
 
 struct RegLayout {
-  int nb, rb, c, b, r0, nrow;
+  int c, b, r0;
   bool act;
   __device__ RegLayout(int a, int t) {
-    nb = min(16, kTriThreads / a);
-    rb = (a + nb - 1) / nb;
-    c = t % a;
-    b = t / a;
-    act = b < nb;
-    r0 = b * rb;
-    nrow = act ? max(0, min(rb, a - r0)) : 0;
+    c = t % kTriLdsMax;
+    b = t / kTriLdsMax;
+    act = b < kRegBlocks && c < a;
+    r0 = (b < kRegBlocks ? b : 0) * kRegRows;
   }
 };
 
@@ -230,42 +233,70 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(const double* __restric
   }
 }
 
+// Sum of n <= 16 LDS values in index order; the loads are issued together.
+__device__ __forceinline__ double lds_sum16(const double* p, int n) {
+  double v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = i < n ? p[i] : 0.0;
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) s += v[i];
+  return s;
+}
+
+__device__ __forceinline__ double lds_sum16_strided(const double* p, int stride, int n) {
+  double v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = i < n ? p[i * stride] : 0.0;
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) s += v[i];
+  return s;
+}
+
 // The same reduction for a <= kTriLdsMax with the matrix in registers
 // (RegLayout; S symmetric, so a thread's column slice is also a row slice).
-// Per step: partial norms of column j -> alpha, tau, v (every thread derives
-// them from the same partials in the same order) -> partial column products
-// of the trailing block with v -> p, K = tau/2 p.v, w -> rank-2 update.
-// v and w live in LDS, zero outside the trailing rows (and in the padding up
-// to nb rb); register slots k >= nrow stay zero.
-constexpr int kPadRows = kTriLdsMax + kRegRows;
-
-__global__ __launch_bounds__(kTriThreads) void k_tridiag_reg(const double* __restrict__ G, int a,
+// Only the trailing rows of a column are updated, so rows above the
+// subdiagonal hold stale values; they are masked where a column is read.
+// Step j, four barriers:
+//   0. the owners of column j have published it (all rows) to colbuf
+//   1. every wavefront derives alpha, tau, v0 from colbuf (one reduction);
+//      wavefront 0 writes the masked reflector v to vbuf and to R
+//   2. partial products of the trailing columns with v
+//   3. p = tau S v per column and the wavefront partials of p.v
+//   4. K = tau/2 p.v and S <- S - v w^T - w v^T with w = p - K v, i.e.
+//      x_r -= v_r (p_c - 2 K v_c) + p_r v_c; the owners of column j+1
+//      publish it
+__global__ __launch_bounds__(kRegThreads) void k_tridiag_reg(const double* __restrict__ G, int a,
                                                              double* __restrict__ R,
                                                              double* __restrict__ tau_out,
                                                              double* __restrict__ d,
                                                              double* __restrict__ e,
                                                              double* __restrict__ misc) {
-  __shared__ double vbuf[kPadRows], wbuf[kPadRows];
-  __shared__ double pd[16 * kTriLdsMax];
-  __shared__ double red[kTriThreads / 64], npart[16];
-  __shared__ double sc_s, x0_s, d_s;
+  constexpr int nw = kRegThreads / 64;
+  __shared__ double colbuf[kPadRows], vbuf[kPadRows], pbuf[kPadRows];
+  __shared__ double pd[kRegBlocks * kTriLdsMax];
+  __shared__ double dl[kTriLdsMax], el[kTriLdsMax], tl[kTriLdsMax];
+  __shared__ double red[nw];
+  __shared__ double sc_s;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const RegLayout L(a, t);
-  const int c = L.c, b = L.b, r0 = L.r0, nrow = L.nrow, nb = L.nb;
+  const int c = L.c, b = L.b, r0 = L.r0;
   const bool act = L.act;
 
-  for (int i = t; i < kPadRows; i += kTriThreads) {
+  for (int i = t; i < kPadRows; i += kRegThreads) {
+    colbuf[i] = 0.0;
     vbuf[i] = 0.0;
-    wbuf[i] = 0.0;
+    pbuf[i] = 0.0;
   }
   double mx = 0.0;
-  for (int i = t; i < a * a; i += kTriThreads) mx = fmax(mx, fabs(G[i]));
+  for (int i = t; i < a * a; i += kRegThreads) mx = fmax(mx, fabs(G[i]));
   mx = wave_max(mx);
   if (lane == 0) red[wv] = mx;
   __syncthreads();
   if (t == 0) {
     double m = 0.0;
-    for (int i = 0; i < kTriThreads / 64; ++i) m = fmax(m, red[i]);
+    for (int i = 0; i < nw; ++i) m = fmax(m, red[i]);
     sc_s = (m > 0.0 && m <= DBL_MAX) ? ldexp(1.0, -ilogb(m)) : 1.0;
     misc[0] = sc_s;
   }
@@ -273,27 +304,25 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag_reg(const double* __res
   const double sc = sc_s;
   double x[kRegRows];
 #pragma unroll
-  for (int k = 0; k < kRegRows; ++k) x[k] = k < nrow ? G[(size_t)c * a + r0 + k] * sc : 0.0;
-  const double* vrow = vbuf + (act ? r0 : 0);
-  const double* wrow = wbuf + (act ? r0 : 0);
+  for (int k = 0; k < kRegRows; ++k) x[k] = (act && r0 + k < a) ? G[(size_t)c * a + r0 + k] * sc : 0.0;
+  const double* vrow = vbuf + r0;
+  const double* prow = pbuf + r0;
+  double* crow = colbuf + r0;
+  if (act && c == 0) {
+#pragma unroll
+    for (int k = 0; k < kRegRows; ++k) crow[k] = x[k];
+  }
+  __syncthreads();
 
   for (int j = 0; j + 2 < a; ++j) {
-    const bool own = act && c == j;
-    if (own) {
-      double sq = 0.0;
-#pragma unroll
-      for (int k = 0; k < kRegRows; ++k) {
-        const int r = r0 + k;
-        if (r > j + 1) sq += x[k] * x[k];
-        if (k < nrow && r == j + 1) x0_s = x[k];
-        if (k < nrow && r == j) d_s = x[k];
-      }
-      npart[b] = sq;
+    // 1. the reflector of column j
+    double sq = 0.0;
+    for (int r = lane; r < kPadRows; r += 64) {
+      const double y = colbuf[r];
+      sq += r > j + 1 ? y * y : 0.0;
     }
-    __syncthreads();
-    double xx = 0.0;
-    for (int bb = 0; bb < nb; ++bb) xx += npart[bb];
-    const double x0 = x0_s;
+    const double xx = wave_sum(sq);
+    const double x0 = colbuf[j + 1];
     double alpha, tau, v0;
     if (xx == 0.0) {
       alpha = x0;
@@ -305,67 +334,89 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag_reg(const double* __res
       v0 = x0 - alpha;
       tau = 2.0 / (v0 * v0 + xx);
     }
-    if (own) {
-#pragma unroll
-      for (int k = 0; k < kRegRows; ++k) {
-        const int r = r0 + k;
-        if (k < nrow) {
-          const double vr = (tau == 0.0 || r <= j) ? 0.0 : (r == j + 1 ? v0 : x[k]);
-          vbuf[r] = vr;
-          if (r > j) R[(size_t)j * a + r] = vr;
-        }
+    if (wv == 0) {
+      for (int r = lane; r < kPadRows; r += 64) {
+        const double vr = (tau == 0.0 || r <= j) ? 0.0 : (r == j + 1 ? v0 : colbuf[r]);
+        vbuf[r] = vr;
+        if (r > j && r < a) R[(size_t)j * a + r] = vr;
+      }
+      if (lane == 0) {
+        tl[j] = tau;
+        el[j] = alpha;
+        dl[j] = colbuf[j];
       }
     }
-    if (t == 0) {
-      tau_out[j] = tau;
-      e[j] = alpha;
-      d[j] = d_s;
-    }
     __syncthreads();
+    const bool live = act && c > j;
     if (tau != 0.0) {
-      const bool live = act && c > j;
+      // 2. partial products with v
+      if (live) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRegRows; k += 2) {
+          s0 += x[k] * vrow[k];
+          s1 += x[k + 1] * vrow[k + 1];
+        }
+        pd[b * kTriLdsMax + c] = s0 + s1;
+      }
+      __syncthreads();
+      // 3. p = tau S v and the partials of p.v
+      double pc = 0.0, vc = 0.0;
       if (live) {
         double sp = 0.0;
 #pragma unroll
-        for (int k = 0; k < kRegRows; ++k) sp += x[k] * vrow[k];
-        pd[b * kTriLdsMax + c] = sp;
-      }
-      __syncthreads();
-      double pc = 0.0, vc = 0.0;
-      if (live) {
-        for (int bb = 0; bb < nb; ++bb) pc += pd[bb * kTriLdsMax + c];
-        pc *= tau;
+        for (int i = 0; i < kRegBlocks; ++i) sp += pd[i * kTriLdsMax + c];
+        pc = tau * sp;
         vc = vbuf[c];
       }
-      double contrib = (live && b == 0) ? pc * vc : 0.0;
-      contrib = wave_sum(contrib);
+      if (act && b == 0) pbuf[c] = pc;
+      const double contrib = wave_sum((live && b == 0) ? pc * vc : 0.0);
       if (lane == 0) red[wv] = contrib;
       __syncthreads();
-      double K = 0.0;
-      for (int i = 0; i < kTriThreads / 64; ++i) K += red[i];
-      K *= 0.5 * tau;
-      const double wc = pc - K * vc;
-      if (act && b == 0) wbuf[c] = live ? wc : 0.0;
-      __syncthreads();
+      // 4. rank-2 update
       if (live) {
+        double kk = 0.0;
 #pragma unroll
-        for (int k = 0; k < kRegRows; ++k)
-          if (k < nrow) x[k] -= vrow[k] * wc + wrow[k] * vc;
+        for (int i = 0; i < nw; ++i) kk += red[i];
+        const double K = 0.5 * tau * kk;
+        const double g = pc - 2.0 * K * vc;
+#pragma unroll
+        for (int k = 0; k < kRegRows; ++k) x[k] = fma(-vrow[k], g, fma(-prow[k], vc, x[k]));
       }
     }
-  }
-  if (act) {
+    if (act && c == j + 1) {
 #pragma unroll
-    for (int k = 0; k < kRegRows; ++k) {
-      const int r = r0 + k;
-      if (k < nrow) {
-        if (c == a - 2 && r == a - 2) d[a - 2] = x[k];
-        if (c == a - 2 && r == a - 1) e[a - 2] = x[k];
-        if (c == a - 1 && r == a - 1) d[a - 1] = x[k];
-      }
+      for (int k = 0; k < kRegRows; ++k) crow[k] = x[k];
     }
+    __syncthreads();
   }
-  if (t == 0) e[a - 1] = 0.0;
+  // the last 2 x 2 block (column a-2 is in colbuf when the loop ran)
+  if (a >= 2) {
+    if (act && c == a - 2) {
+#pragma unroll
+      for (int k = 0; k < kRegRows; ++k) crow[k] = x[k];
+    }
+    __syncthreads();
+    if (t == 0) {
+      d[a - 2] = colbuf[a - 2];
+      e[a - 2] = colbuf[a - 1];
+    }
+    __syncthreads();
+  }
+  if (act && c == a - 1) {
+#pragma unroll
+    for (int k = 0; k < kRegRows; ++k) crow[k] = x[k];
+  }
+  __syncthreads();
+  if (t == 0) {
+    d[a - 1] = colbuf[a - 1];
+    e[a - 1] = 0.0;
+  }
+  for (int i = t; i + 2 < a; i += kRegThreads) {
+    tau_out[i] = tl[i];
+    e[i] = el[i];
+    d[i] = dl[i];
+  }
 }
 
 // Number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots);
@@ -679,77 +730,81 @@ __global__ __launch_bounds__(kTriThreads) void k_mgs(int a, const double* __rest
 }
 
 // Modified Gram-Schmidt for a <= kTriLdsMax with the columns in registers
-// (RegLayout).  Step j: the owners of column j publish it and its squared
-// norm (block partials); every thread forms its partial product with its
-// column, the partials of a column are summed in block order, and the
-// column is updated.  A second pass runs only when some pair of columns of
-// the first pass had |cos| > 1e-3 (one pass of Gram-Schmidt then already
-// leaves them orthogonal to rounding level).  Xin is [row][column], Xo
-// column-major.
-__global__ __launch_bounds__(kTriThreads) void k_mgs_reg(int a, const double* __restrict__ Xin,
+// (RegLayout).  Step j: the owners of column j have published it (double
+// buffered) with the block partials of its squared norm; every thread forms
+// its partial product with its column, the partials of a column are summed
+// in block order, and the column is updated.  A second pass runs only when
+// some pair of columns of the first pass had |cos| > 1e-3 (below that one
+// pass already leaves them orthogonal to rounding level).  Xin is
+// [row][column], Xo column-major.
+__global__ __launch_bounds__(kRegThreads) void k_mgs_reg(int a, const double* __restrict__ Xin,
                                                          double* __restrict__ Xo) {
-  __shared__ double qbuf[kTriLdsMax];
-  __shared__ double pd[16 * kTriLdsMax];
-  __shared__ double np[16];
-  __shared__ double red[kTriThreads / 64];
+  constexpr int nw = kRegThreads / 64;
+  __shared__ double qbuf[2][kPadRows];
+  __shared__ double pd[kRegBlocks * kTriLdsMax];
+  __shared__ double np[kRegBlocks];
+  __shared__ double red[nw];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const RegLayout L(a, t);
-  const int c = L.c, b = L.b, r0 = L.r0, nrow = L.nrow, nb = L.nb;
+  const int c = L.c, b = L.b, r0 = L.r0;
   const bool act = L.act;
   double x[kRegRows];
 #pragma unroll
-  for (int k = 0; k < kRegRows; ++k) x[k] = k < nrow ? Xin[(size_t)(r0 + k) * a + c] : 0.0;
+  for (int k = 0; k < kRegRows; ++k) x[k] = (act && r0 + k < a) ? Xin[(size_t)(r0 + k) * a + c] : 0.0;
   for (int pass = 0; pass < 2; ++pass) {
     double cmax = 0.0;  // largest |cos| between column c and an earlier column
-    if (act && c == 0) {
-      double s = 0.0;
+    double cur = 0.0;   // squared norm of column c, tracked through the updates
 #pragma unroll
-      for (int k = 0; k < kRegRows; ++k) {
-        if (k < nrow) qbuf[r0 + k] = x[k];
-        s += x[k] * x[k];
-      }
-      np[b] = s;
+    for (int k = 0; k < kRegRows; ++k) cur += x[k] * x[k];
+    if (act && c == 0) {
+#pragma unroll
+      for (int k = 0; k < kRegRows; ++k) qbuf[0][r0 + k] = x[k];
+      np[b] = cur;
     }
     __syncthreads();
     double mynorm = 0.0;
     for (int j = 0; j + 1 < a; ++j) {
       double nj = 0.0;
-      for (int bb = 0; bb < nb; ++bb) nj += np[bb];
+#pragma unroll
+      for (int i = 0; i < kRegBlocks; ++i) nj += np[i];
       if (c == j) mynorm = nj;
       const bool live = act && c > j;
-      double q[kRegRows];
-#pragma unroll
-      for (int k = 0; k < kRegRows; ++k) q[k] = (live && k < nrow) ? qbuf[r0 + k] : 0.0;
+      const double* q = qbuf[j & 1] + r0;
       if (live) {
-        double sp = 0.0;
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int k = 0; k < kRegRows; ++k) sp += q[k] * x[k];
-        pd[b * kTriLdsMax + c] = sp;
+        for (int k = 0; k < kRegRows; k += 2) {
+          s0 += q[k] * x[k];
+          s1 += q[k + 1] * x[k + 1];
+        }
+        pd[b * kTriLdsMax + c] = s0 + s1;
       }
       __syncthreads();
       if (live) {
         double dot = 0.0;
-        for (int bb = 0; bb < nb; ++bb) dot += pd[bb * kTriLdsMax + c];
+#pragma unroll
+        for (int i = 0; i < kRegBlocks; ++i) dot += pd[i * kTriLdsMax + c];
         const double coef = nj > 0.0 ? dot / nj : 0.0;
-        double s = 0.0, before = 0.0;
+        if (pass == 0 && nj > 0.0 && cur > 0.0) cmax = fmax(cmax, fabs(dot) * rsqrt(nj) * rsqrt(cur));
 #pragma unroll
-        for (int k = 0; k < kRegRows; ++k) {
-          before += x[k] * x[k];
-          x[k] -= coef * q[k];
-          s += x[k] * x[k];
-        }
-        if (pass == 0 && nj > 0.0 && before > 0.0) cmax = fmax(cmax, fabs(dot) * rsqrt(nj) * rsqrt(before));
+        for (int k = 0; k < kRegRows; ++k) x[k] = fma(-coef, q[k], x[k]);
+        cur = fmax(cur - dot * coef, 0.0);
         if (c == j + 1) {
+          double s = 0.0;
+          double* qn = qbuf[(j + 1) & 1] + r0;
 #pragma unroll
-          for (int k = 0; k < kRegRows; ++k)
-            if (k < nrow) qbuf[r0 + k] = x[k];
+          for (int k = 0; k < kRegRows; ++k) {
+            qn[k] = x[k];
+            s += x[k] * x[k];
+          }
           np[b] = s;
         }
       }
       __syncthreads();
     }
     double nl = 0.0;
-    for (int bb = 0; bb < nb; ++bb) nl += np[bb];
+#pragma unroll
+    for (int i = 0; i < kRegBlocks; ++i) nl += np[i];
     if (c == a - 1) mynorm = nl;
     const double sc = mynorm > 0.0 ? 1.0 / sqrt(mynorm) : 0.0;
 #pragma unroll
@@ -759,14 +814,15 @@ __global__ __launch_bounds__(kTriThreads) void k_mgs_reg(int a, const double* __
     if (lane == 0) red[wv] = cmax;
     __syncthreads();
     double cm = 0.0;
-    for (int i = 0; i < kTriThreads / 64; ++i) cm = fmax(cm, red[i]);
+#pragma unroll
+    for (int i = 0; i < nw; ++i) cm = fmax(cm, red[i]);
     if (pass == 0 && cm <= 1e-3) break;
     __syncthreads();
   }
   if (act) {
 #pragma unroll
     for (int k = 0; k < kRegRows; ++k)
-      if (k < nrow) Xo[(size_t)c * a + r0 + k] = x[k];
+      if (r0 + k < a) Xo[(size_t)c * a + r0 + k] = x[k];
   }
 }
 
@@ -822,7 +878,7 @@ void sym_eig(hipStream_t s, const double* G, int a, double* V, double* w, double
   double* X = LU + 5 * aa;
   double* Xo = X + aa;
   if (a <= kTriLdsMax) {
-    hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(kTriThreads), 0, s, G, a, R, tau, d, e, misc);
+    hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(kRegThreads), 0, s, G, a, R, tau, d, e, misc);
   } else {
     hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kTriThreads), sizeof(double) * 6 * a, s, G, a, S, R, tau, d,
                        e, misc);
@@ -839,7 +895,7 @@ void sym_eig(hipStream_t s, const double* G, int a, double* V, double* w, double
   }
   check("sym_eig invit");
   if (a <= kTriLdsMax) {
-    hipLaunchKernelGGL(k_mgs_reg, dim3(1), dim3(kTriThreads), 0, s, a, X, Xo);
+    hipLaunchKernelGGL(k_mgs_reg, dim3(1), dim3(kRegThreads), 0, s, a, X, Xo);
   } else {
     hipLaunchKernelGGL(k_mgs, dim3(1), dim3(kTriThreads), sizeof(double) * a, s, a, X, Xo, S);
   }
