@@ -197,6 +197,17 @@ tk_status tucker_truncate(tk_ctx* ctx, const tk_tucker* y, double eps, tk_tucker
  * Asynchronous on the context's stream. */
 tk_status tk_sym_eig(tk_ctx* ctx, const double* G, int32_t a, double* V, double* w);
 
+/* C = alpha op(A) op(B) + beta C (op = transpose when ta / tb is nonzero),
+ * column-major, FP64: the dense contraction behind the mode products of
+ * eq. tt_product and the Tucker scalar products, on the library's matrix-core
+ * GEMM (K split over workgroups when the output has few tiles).  A, B, C are
+ * device memory owned by the caller; lda >= rows of A as stored (M, or K
+ * when transposed), likewise ldb, and ldc >= M.  With beta = 0, C is not
+ * read.  Asynchronous on the context's stream. */
+tk_status tk_dgemm(tk_ctx* ctx, int32_t ta, int32_t tb, int32_t M, int32_t N, int32_t K, double alpha,
+                   const double* A, int32_t lda, const double* B, int32_t ldb, double beta, double* C,
+                   int32_t ldc);
+
 /* ---- solver (Algorithm 5) -------------------------------------------------- */
 
 typedef struct {

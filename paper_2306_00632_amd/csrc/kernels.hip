@@ -94,19 +94,33 @@ void band_apply(hipStream_t s, int n, int m, int nmat, int p, const double* band
 // FP64 GEMM
 // ---------------------------------------------------------------------------
 
-constexpr int BM = 64, BN = 64, BK = 16;
+// FP64 GEMM on the matrix cores (v_mfma_f64_16x16x4f64).  A workgroup of
+// four wavefronts computes a BM x (16 NT) tile of C; wavefront w owns rows
+// [16w, 16w+16) and NT column tiles of 16, i.e. NT 16x16 accumulators.  K is
+// staged through LDS in steps of BK = 16 (double buffered: the next step's
+// global loads are in flight while the current step is multiplied).
+// Operand layout of the instruction (lane l, element v): A[l%16][l/16],
+// B[l/16][l%16], D[l/16 + 4v][l%16].
+constexpr int BM = 64, BK = 16;
+constexpr int kAPad = BM + 1;  // odd row strides keep the transposing LDS stores conflict-free
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // With `part` set, blockIdx.z selects the K range [z*kchunk, (z+1)*kchunk)
 // and alpha*op(A)op(B) over that range is written to part + z*M*N (ld M);
 // otherwise blockIdx.z is the batch index.
-template <bool TA, bool TB>
+template <bool TA, bool TB, int NT>
 __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha,
                                                const double* __restrict__ A, int lda, long long sA,
                                                const double* __restrict__ B, int ldb, long long sB,
                                                double beta, double* __restrict__ C, int ldc,
                                                long long sC, int kchunk, double* __restrict__ part) {
-  __shared__ double As[BK][BM + 1];
-  __shared__ double Bs[BK][BN + 1];
+  constexpr int BN = 16 * NT;
+  constexpr int kBPad = BN + 1;
+  constexpr int kALoads = BM * BK / 256;  // 4
+  constexpr int kBLoads = BN * BK / 256;  // NT
+  __shared__ double As[2][BK][kAPad];
+  __shared__ double Bs[2][BK][kBPad];
   int kbeg = 0, kend = K;
   if (part) {
     kbeg = blockIdx.z * kchunk;
@@ -119,61 +133,77 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
     B += sB * blockIdx.z;
     C += sC * blockIdx.z;
   }
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int row0 = blockIdx.x * BM, col0 = blockIdx.y * BN;
-  double acc[4][4];
+  double ra[kALoads], rb[kBLoads];
+  auto load = [&](int k0) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // A tile: op(A)[row0 + i][k0 + kk]
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      const int e = threadIdx.x + 256 * l;
-      int i, kk;
-      if (!TA) { i = e & (BM - 1); kk = e >> 6; } else { kk = e & (BK - 1); i = e >> 4; }
+    for (int l = 0; l < kALoads; ++l) {
+      const int e = t + 256 * l;
+      const int i = TA ? e / BK : e % BM, kk = TA ? e % BK : e / BM;
       const int gr = row0 + i, gk = k0 + kk;
-      double v = 0.0;
-      if (gr < M && gk < kend) v = TA ? A[gk + (long long)gr * lda] : A[gr + (long long)gk * lda];
-      As[kk][i] = v;
+      ra[l] = (gr < M && gk < kend) ? (TA ? A[gk + (long long)gr * lda] : A[gr + (long long)gk * lda]) : 0.0;
     }
-    // B tile: op(B)[k0 + kk][col0 + j]
 #pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      const int e = threadIdx.x + 256 * l;
-      int j, kk;
-      if (!TB) { kk = e & (BK - 1); j = e >> 4; } else { j = e & (BN - 1); kk = e >> 6; }
+    for (int l = 0; l < kBLoads; ++l) {
+      const int e = t + 256 * l;
+      const int j = TB ? e % BN : e / BK, kk = TB ? e / BN : e % BK;
       const int gc = col0 + j, gk = k0 + kk;
-      double v = 0.0;
-      if (gc < N && gk < kend) v = TB ? B[gc + (long long)gk * ldb] : B[gk + (long long)gc * ldb];
-      Bs[kk][j] = v;
+      rb[l] = (gc < N && gk < kend) ? (TB ? B[gc + (long long)gk * ldb] : B[gk + (long long)gc * ldb]) : 0.0;
     }
-    __syncthreads();
+  };
+  auto store = [&](int buf) {
 #pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tx + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][ty + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    for (int l = 0; l < kALoads; ++l) {
+      const int e = t + 256 * l;
+      const int i = TA ? e / BK : e % BM, kk = TA ? e % BK : e / BM;
+      As[buf][kk][i] = ra[l];
     }
+#pragma unroll
+    for (int l = 0; l < kBLoads; ++l) {
+      const int e = t + 256 * l;
+      const int j = TB ? e % BN : e / BK, kk = TB ? e / BN : e % BK;
+      Bs[buf][kk][j] = rb[l];
+    }
+  };
+  dbl4 acc[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int fr = 16 * wv + (lane & 15);  // A fragment row within the tile
+  const int fk = lane >> 4;              // fragment k within a step of 4
+  const int fc = lane & 15;              // B fragment column within a 16-wide tile
+  int buf = 0;
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) load(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const double af = As[buf][ks + fk][fr];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const double bf = Bs[buf][ks + fk][16 * j + fc];
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc[j], 0, 0, 0);
+      }
+    }
+    if (more) store(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int gc = col0 + ty + 16 * j;
+  for (int j = 0; j < NT; ++j) {
+    const int gc = col0 + 16 * j + fc;
     if (gc >= N) continue;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int gr = row0 + tx + 16 * i;
+    for (int v = 0; v < 4; ++v) {
+      const int gr = row0 + 16 * wv + (lane >> 4) + 4 * v;
       if (gr >= M) continue;
       double* cp = C + gr + (long long)gc * ldc;
-      *cp = (beta == 0.0) ? alpha * acc[i][j] : alpha * acc[i][j] + beta * (*cp);
+      *cp = (beta == 0.0) ? alpha * acc[j][v] : alpha * acc[j][v] + beta * (*cp);
     }
   }
 }
@@ -190,11 +220,25 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(int M, int N, int nsplit,
   }
 }
 
+// column tiles of 16 per workgroup for an N-wide product
+static int dgemm_nt(int N) { return N <= 32 ? 2 : N <= 64 ? 4 : N <= 96 ? 6 : 9; }
+
 int dgemm_split_count(int M, int N, int K) {
-  const long long tiles = (long long)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  const int bn = 16 * dgemm_nt(N);
+  const long long tiles = (long long)((M + BM - 1) / BM) * ((N + bn - 1) / bn);
   if (tiles >= 128 || K < 1024) return 1;
   long long ns = std::min<long long>(K / 256, 256 / std::max<long long>(tiles, 1));
   return (int)std::max<long long>(1, std::min<long long>(ns, 64));
+}
+
+template <int NT>
+static void launch_dgemm(hipStream_t s, bool ta, bool tb, dim3 grid, int M, int N, int K, double alpha,
+                         const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
+                         double beta, double* C, int ldc, long long sC, int kchunk, double* part) {
+  if (!ta && !tb) hipLaunchKernelGGL((k_dgemm<false, false, NT>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
+  else if (ta && !tb) hipLaunchKernelGGL((k_dgemm<true, false, NT>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
+  else if (!ta && tb) hipLaunchKernelGGL((k_dgemm<false, true, NT>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
+  else hipLaunchKernelGGL((k_dgemm<true, true, NT>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
 }
 
 void dgemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
@@ -216,11 +260,14 @@ void dgemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
   } else {
     part = nullptr;
   }
-  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, gz);
-  if (!ta && !tb) hipLaunchKernelGGL((k_dgemm<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
-  else if (ta && !tb) hipLaunchKernelGGL((k_dgemm<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
-  else if (!ta && tb) hipLaunchKernelGGL((k_dgemm<false, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
-  else hipLaunchKernelGGL((k_dgemm<true, true>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
+  const int nt = dgemm_nt(N);
+  dim3 grid((M + BM - 1) / BM, (N + 16 * nt - 1) / (16 * nt), gz);
+  switch (nt) {
+    case 2: launch_dgemm<2>(s, ta, tb, grid, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part); break;
+    case 4: launch_dgemm<4>(s, ta, tb, grid, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part); break;
+    case 6: launch_dgemm<6>(s, ta, tb, grid, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part); break;
+    default: launch_dgemm<9>(s, ta, tb, grid, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part); break;
+  }
   check_launch("dgemm");
   if (part) {
     const long long MN = (long long)M * N;

@@ -1177,6 +1177,21 @@ tk_status tk_sym_eig(tk_ctx* ctx, const double* G, int32_t a, double* V, double*
   });
 }
 
+tk_status tk_dgemm(tk_ctx* ctx, int32_t ta, int32_t tb, int32_t M, int32_t N, int32_t K, double alpha,
+                   const double* A, int32_t lda, const double* B, int32_t ldb, double beta, double* C,
+                   int32_t ldc) {
+  if (!ctx || M < 0 || N < 0 || K < 0) return TK_EINVAL;
+  if ((M > 0 && N > 0) && (!C || ldc < M)) return TK_EINVAL;
+  if (M > 0 && N > 0 && K > 0) {
+    if (!A || !B) return TK_EINVAL;
+    if (lda < (ta ? K : M) || ldb < (tb ? N : K)) return TK_EINVAL;
+  }
+  return guarded(ctx, [&]() {
+    gemm(ctx, ta != 0, tb != 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    return TK_OK;
+  });
+}
+
 void tk_tpcg_defaults(tk_tpcg_params* p) {
   if (!p) return;
   p->tol = 1e-6;

@@ -73,6 +73,8 @@ EXPORTS = {
     "tucker_truncate": (C.c_int32, [vp, vp, C.c_double, C.POINTER(vp), dp]),
     "tk_tpcg_defaults": (None, [C.POINTER(TpcgParams)]),
     "tk_sym_eig": (C.c_int32, [vp, vp, C.c_int32, vp, vp]),
+    "tk_dgemm": (C.c_int32, [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                             vp, C.c_int32, vp, C.c_int32, C.c_double, vp, C.c_int32]),
     "tk_prof_enable": (C.c_int32, [vp, C.c_int32]),
     "tk_prof_reset": (C.c_int32, [vp]),
     "tk_prof_read": (C.c_int32, [vp, C.c_int32, i64p, dp, dp, dp]),
@@ -409,6 +411,18 @@ def sym_eig(ctx, G_dev, a: int, V_dev, w_dev) -> None:
             raise ValueError("sym_eig needs contiguous float64 device tensors of the right size")
     ctx.check(lib().tk_sym_eig(ctx.h, vp(G_dev.data_ptr()), a, vp(V_dev.data_ptr()),
                                vp(w_dev.data_ptr())), "tk_sym_eig")
+
+
+def dgemm(ctx, ta: bool, tb: bool, M: int, N: int, K: int, alpha: float, A_dev, lda: int,
+          B_dev, ldb: int, beta: float, C_dev, ldc: int) -> None:
+    """C = alpha op(A) op(B) + beta C on device float64 tensors (column-major
+    storage, leading dimensions as in BLAS).  Asynchronous."""
+    import torch
+    for t in (A_dev, B_dev, C_dev):
+        if t.dtype != torch.float64 or not t.is_cuda:
+            raise ValueError("dgemm needs float64 device tensors")
+    ctx.check(lib().tk_dgemm(ctx.h, int(ta), int(tb), M, N, K, alpha, vp(A_dev.data_ptr()), lda,
+                             vp(B_dev.data_ptr()), ldb, beta, vp(C_dev.data_ptr()), ldc), "tk_dgemm")
 
 
 def tpcg_params(**kw) -> TpcgParams:
