@@ -273,6 +273,16 @@ static void gemm(tk_ctx* ctx, bool ta, bool tb, int M, int N, int K, double alph
              part ? part->p : nullptr, ns);
 }
 
+// batched C_i = alpha op(A_i) op(B_i) + beta C_i with element strides
+static void gemm_batched(tk_ctx* ctx, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+                         int lda, long long sA, const double* B, int ldb, long long sB, double beta, double* C,
+                         int ldc, long long sC, int batch) {
+  Prof pr(ctx, PK_GEMM,
+          8.0 * batch * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1)),
+          2.0 * batch * M * N * (double)K);
+  gpu::dgemm(ctx->stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, nullptr, 1);
+}
+
 // ---------------------------------------------------------------------------
 // Tucker objects
 // ---------------------------------------------------------------------------
@@ -422,35 +432,47 @@ static TruncPrep truncate_prepare(tk_ctx* ctx, const tk_tucker* y) {
     Prof pr(ctx, PK_QR, by, fl);
     gpu::householder_qr(ctx->stream, jobs, nj);
   }
-  // Z = sum_b c_b G_b x_1 R_1[:, b] x_2 R_2[:, b] x_3 R_3[:, b]
+  // Z = sum_b c_b G_b x_1 R_1[:, b] x_2 R_2[:, b] x_3 R_3[:, b], as one
+  // contraction over the stacked mode-1 rank: every block writes
+  // W_b = c_b G_b x_2 R_2[:, b] x_3 R_3[:, b] (r1_b x q1 q2, mode-1 unfolding)
+  // into rows off1_b.. of W (m1 x q1 q2), then Z_(1) = R_1 W.
   const long long zsz = (long long)P.q[0] * P.q[1] * P.q[2];
   P.Z = alloc(ctx, (size_t)std::max<long long>(zsz, 1));
-  gpu::fill(ctx->stream, P.Z->p, zsz, 0.0);
-  for (const auto& b : y->blocks) {
-    if (prod3(b.r) == 0 || zsz == 0) continue;
-    const double* M[3];
-    int ldm[3];
-    for (int k = 0; k < 3; ++k) {
-      M[k] = R[k]->p + (size_t)b.off[k] * P.q[k];
-      ldm[k] = P.q[k];
-    }
-    // first two contractions, then accumulate the third directly into Z
-    int dims[3] = {b.r[0], b.r[1], b.r[2]};
-    const double* cur = b.core->p;
-    BufP hold;
-    for (int k = 0; k < 2; ++k) {
-      const int a = dims[0], bc = dims[1] * dims[2];
-      BufP out = alloc(ctx, (size_t)bc * P.q[k]);
-      gemm(ctx, true, true, bc, P.q[k], a, 1.0, cur, a, M[k], ldm[k], 0.0, out->p, bc);
-      hold = out;
-      cur = out->p;
-      dims[0] = dims[1];
-      dims[1] = dims[2];
-      dims[2] = P.q[k];
-    }
-    const int a = dims[0], bc = dims[1] * dims[2];  // a = r2, bc = q0 q1
-    gemm(ctx, true, true, bc, P.q[2], a, b.c, cur, a, M[2], ldm[2], 1.0, P.Z->p, bc);
+  const int m1 = y->m[0];
+  const long long q12 = (long long)P.q[1] * P.q[2];
+  if (zsz == 0) return P;
+  if (m1 == 0) {
+    gpu::fill(ctx->stream, P.Z->p, zsz, 0.0);
+    return P;
   }
+  // blocks whose mode-1 column ranges tile [0, m1) exactly can be written
+  // with beta = 0; otherwise W starts at zero and blocks accumulate
+  std::vector<std::pair<int, int>> ranges;
+  for (const auto& b : y->blocks)
+    if (prod3(b.r) > 0) ranges.push_back({b.off[0], b.r[0]});
+  std::sort(ranges.begin(), ranges.end());
+  bool tiles = true;
+  int next = 0;
+  for (const auto& rg : ranges) {
+    if (rg.first != next) tiles = false;
+    next = rg.first + rg.second;
+  }
+  if (next != m1) tiles = false;
+  BufP W = alloc(ctx, (size_t)m1 * q12);
+  if (!tiles) gpu::fill(ctx->stream, W->p, (long long)m1 * q12, 0.0);
+  for (const auto& b : y->blocks) {
+    if (prod3(b.r) == 0) continue;
+    const int r1 = b.r[0], r2 = b.r[1], r3 = b.r[2];
+    const double* R2 = R[1]->p + (size_t)b.off[1] * P.q[1];
+    const double* R3 = R[2]->p + (size_t)b.off[2] * P.q[2];
+    // T = G_b x_3 R_3[:, b]: (r1 r2 x r3) (q2 x r3)^T
+    BufP T = alloc(ctx, (size_t)r1 * r2 * P.q[2]);
+    gemm(ctx, false, true, r1 * r2, P.q[2], r3, 1.0, b.core->p, r1 * r2, R3, P.q[2], 0.0, T->p, r1 * r2);
+    // W_b[:, :, i2] = c_b T[:, :, i2] R_2[:, b]^T for every i2
+    gemm_batched(ctx, false, true, r1, P.q[1], r2, b.c, T->p, r1, (long long)r1 * r2, R2, P.q[1], 0,
+                 tiles ? 0.0 : 1.0, W->p + b.off[0], m1, (long long)m1 * P.q[1], P.q[2]);
+  }
+  gemm(ctx, false, false, P.q[0], (int)q12, m1, 1.0, R[0]->p, P.q[0], W->p, m1, 0.0, P.Z->p, P.q[0]);
   return P;
 }
 
