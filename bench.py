@@ -30,6 +30,29 @@ sys.path.insert(0, ROOT)
 METRIC = "TPCG solves/sec + p50/p99 latency at rel. err 1e-6; HBM GB/s of mode products"
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+# source file holding the kernels of each instrumented family
+FAMILY_SOURCE = {"sym_eig": "eig.hip", "dgemm": "kernels.hip", "band_apply": "kernels.hip",
+                 "select_rank": "kernels.hip", "fd_forward": "kernels.hip", "fd_backward": "kernels.hip",
+                 "householder_qr": "kernels.hip"}
+
+
+def measured_traffic(family):
+    """HBM bytes per launch of a kernel family from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when none was taken or the
+    family's kernel source has changed since (sha256 of the source file)."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh).get(family)
+    except (OSError, ValueError):
+        return None
+    if not rec or family not in FAMILY_SOURCE:
+        return None
+    src = os.path.join(ROOT, "paper_2306_00632_amd", "csrc", FAMILY_SOURCE[family])
+    with open(src, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    return rec["bytes_per_launch"] if digest == rec.get("source_sha256") else None
 
 
 def workload(name):
@@ -75,6 +98,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="deformed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run one plain device copy of MIB MiB (read + write) before the solves, "
+                         "as the known-size reference of a rocprofv3 FETCH_SIZE/WRITE_SIZE run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a TPCG solve is not split "
@@ -87,6 +113,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     w = workload(args.workload)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = tk.Context(0)
     op = problem.operator(ctx, w)
     prec = problem.preconditioner(ctx, w)
@@ -130,12 +164,12 @@ def main():
     if dom in ("band_apply", "fd_forward", "fd_backward", "select_rank"):
         achieved = dk["bytes"] / dk["launches"] / (dk["ms"] / dk["launches"] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+                "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(dom)}
     else:
         achieved = dk["flops"] / dk["launches"] / (dk["ms"] / dk["launches"] / 1e3) / 1e12
         roof = {"bound": "alu" if dom != "dgemm" else "mfma", "achieved": achieved,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": None}
+                "traffic": measured_traffic(dom)}
     roof["kernel"] = dom
     roof["avg_launch_us"] = 1e3 * dk["ms"] / dk["launches"]
     mp = kern["band_apply"]
