@@ -90,26 +90,36 @@ __device__ __forceinline__ double recip(double q) {
 }
 
 // Register-resident layout of an a x a matrix (a <= kTriLdsMax) in one
-// workgroup of kRegThreads threads: thread t = b kTriLdsMax + c holds column
-// c (< a) for the kRegRows rows [b kRegRows, (b+1) kRegRows), b < kRegBlocks.
-// Rows at or beyond a are zero padding (in registers and in the LDS vectors
-// they meet), so the per-row loops have compile-time bounds and no tests.
+// workgroup of kRegThreads threads: the four lanes of a quad hold one column,
+// lane b of the quad the kRegRows rows [b kRegRows, (b+1) kRegRows); wavefront
+// w holds columns [16w, 16w+16).  Reductions over a column are two DPP quad
+// permutes, with no LDS and no barrier.  Rows at or beyond a are zero padding
+// (in registers and in the LDS vectors they meet), so the per-row loops have
+// compile-time bounds and no tests.
 constexpr int kRegBlocks = 4;
 constexpr int kRegRows = 34;  // kRegBlocks * kRegRows >= kTriLdsMax
-constexpr int kRegThreads = 576;  // >= kRegBlocks * kTriLdsMax, whole wavefronts
+constexpr int kRegThreads = 576;  // 9 wavefronts x 16 columns >= kTriLdsMax
 constexpr int kPadRows = kRegBlocks * kRegRows;
 static_assert(kPadRows >= kTriLdsMax, "row blocks must cover kTriLdsMax rows");
+static_assert(kRegThreads / 4 >= kTriLdsMax, "one quad per column");
 
 struct RegLayout {
   int c, b, r0;
   bool act;
   __device__ RegLayout(int a, int t) {
-    c = t % kTriLdsMax;
-    b = t / kTriLdsMax;
-    act = b < kRegBlocks && c < a;
-    r0 = (b < kRegBlocks ? b : 0) * kRegRows;
+    c = t >> 2;
+    b = t & 3;
+    act = c < a;
+    r0 = b * kRegRows;
   }
 };
+
+// sum over the four lanes of a quad (all four hold the result, bitwise equal)
+__device__ __forceinline__ double quad_sum(double v) {
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  return v;
+}
 
 // SplitMix64 finaliser (Steele, Lea, Flood 2014) mapped to [-1, 1)
 __device__ inline double unit_rand(unsigned long long key) {
@@ -255,18 +265,17 @@ __device__ __forceinline__ double lds_sum16_strided(const double* p, int stride,
 }
 
 // The same reduction for a <= kTriLdsMax with the matrix in registers
-// (RegLayout; S symmetric, so a thread's column slice is also a row slice).
-// Only the trailing rows of a column are updated, so rows above the
-// subdiagonal hold stale values; they are masked where a column is read.
-// Step j, four barriers:
-//   0. the owners of column j have published it (all rows) to colbuf
-//   1. every wavefront derives alpha, tau, v0 from colbuf (one reduction);
-//      wavefront 0 writes the masked reflector v to vbuf and to R
-//   2. partial products of the trailing columns with v
-//   3. p = tau S v per column and the wavefront partials of p.v
-//   4. K = tau/2 p.v and S <- S - v w^T - w v^T with w = p - K v, i.e.
-//      x_r -= v_r (p_c - 2 K v_c) + p_r v_c; the owners of column j+1
-//      publish it
+// (RegLayout; S symmetric, so a column slice is also a row slice).  Only the
+// trailing rows of a column are updated, so rows above the subdiagonal hold
+// stale values; they are masked where a column is read.  Step j, two
+// barriers:
+//   P  p_c = tau (S v)_c for the trailing columns (quad reduction), p to
+//      LDS, wavefront partials of p.v
+//   U  K = tau/2 p.v, S <- S - v w^T - w v^T with w = p - K v, i.e.
+//      x_r -= v_r (p_c - 2 K v_c) + p_r v_c; then the wavefront owning
+//      column j+1 derives the next reflector from its registers and
+//      publishes it (v, tau double buffered by step parity)
+// d, e and tau are staged in LDS and written, with the reflectors, at the end.
 __global__ __launch_bounds__(kRegThreads) void k_tridiag_reg(const double* __restrict__ G, int a,
                                                              double* __restrict__ R,
                                                              double* __restrict__ tau_out,
@@ -274,10 +283,9 @@ __global__ __launch_bounds__(kRegThreads) void k_tridiag_reg(const double* __res
                                                              double* __restrict__ e,
                                                              double* __restrict__ misc) {
   constexpr int nw = kRegThreads / 64;
-  __shared__ double colbuf[kPadRows], vbuf[kPadRows], pbuf[kPadRows];
-  __shared__ double pd[kRegBlocks * kTriLdsMax];
+  __shared__ double vbuf[2][kPadRows], pbuf[kPadRows], colbuf[kPadRows];
   __shared__ double dl[kTriLdsMax], el[kTriLdsMax], tl[kTriLdsMax];
-  __shared__ double red[nw];
+  __shared__ double red[nw], tau_s[2];
   __shared__ double sc_s;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const RegLayout L(a, t);
@@ -285,9 +293,10 @@ __global__ __launch_bounds__(kRegThreads) void k_tridiag_reg(const double* __res
   const bool act = L.act;
 
   for (int i = t; i < kPadRows; i += kRegThreads) {
-    colbuf[i] = 0.0;
-    vbuf[i] = 0.0;
+    vbuf[0][i] = 0.0;
+    vbuf[1][i] = 0.0;
     pbuf[i] = 0.0;
+    colbuf[i] = 0.0;
   }
   double mx = 0.0;
   for (int i = t; i < a * a; i += kRegThreads) mx = fmax(mx, fabs(G[i]));
@@ -305,24 +314,25 @@ __global__ __launch_bounds__(kRegThreads) void k_tridiag_reg(const double* __res
   double x[kRegRows];
 #pragma unroll
   for (int k = 0; k < kRegRows; ++k) x[k] = (act && r0 + k < a) ? G[(size_t)c * a + r0 + k] * sc : 0.0;
-  const double* vrow = vbuf + r0;
   const double* prow = pbuf + r0;
-  double* crow = colbuf + r0;
-  if (act && c == 0) {
-#pragma unroll
-    for (int k = 0; k < kRegRows; ++k) crow[k] = x[k];
-  }
-  __syncthreads();
 
-  for (int j = 0; j + 2 < a; ++j) {
-    // 1. the reflector of column j
-    double sq = 0.0;
-    for (int r = lane; r < kPadRows; r += 64) {
-      const double y = colbuf[r];
-      sq += r > j + 1 ? y * y : 0.0;
+  // Reflector of column jj, run by the whole wavefront that owns it: the
+  // owner quad writes the column to LDS, then all 64 lanes take three rows
+  // each (masked norm below the subdiagonal, v, the stored reflector).
+  auto reflector = [&](int jj) {
+    if (act && c == jj) {
+#pragma unroll
+      for (int k = 0; k < kRegRows; ++k) colbuf[r0 + k] = x[k];
+    }
+    double col[3], sq = 0.0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int r = lane + 64 * m;
+      col[m] = r < kPadRows ? colbuf[r] : 0.0;
+      if (r > jj + 1) sq += col[m] * col[m];
     }
     const double xx = wave_sum(sq);
-    const double x0 = colbuf[j + 1];
+    const double x0 = colbuf[jj + 1];
     double alpha, tau, v0;
     if (xx == 0.0) {
       alpha = x0;
@@ -334,46 +344,46 @@ __global__ __launch_bounds__(kRegThreads) void k_tridiag_reg(const double* __res
       v0 = x0 - alpha;
       tau = 2.0 / (v0 * v0 + xx);
     }
-    if (wv == 0) {
-      for (int r = lane; r < kPadRows; r += 64) {
-        const double vr = (tau == 0.0 || r <= j) ? 0.0 : (r == j + 1 ? v0 : colbuf[r]);
-        vbuf[r] = vr;
-        if (r > j && r < a) R[(size_t)j * a + r] = vr;
-      }
-      if (lane == 0) {
-        tl[j] = tau;
-        el[j] = alpha;
-        dl[j] = colbuf[j];
-      }
+    double* vb = vbuf[jj & 1];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int r = lane + 64 * m;
+      const double vr = (tau == 0.0 || r <= jj) ? 0.0 : (r == jj + 1 ? v0 : col[m]);
+      if (r < kPadRows) vb[r] = vr;
+      if (r > jj && r < a) R[(size_t)jj * a + r] = vr;
     }
-    __syncthreads();
+    if (lane == 0) {
+      tau_s[jj & 1] = tau;
+      tl[jj] = tau;
+      el[jj] = alpha;
+      dl[jj] = colbuf[jj];
+    }
+  };
+  if (a > 2 && wv == 0) reflector(0);
+  __syncthreads();
+
+  for (int j = 0; j + 2 < a; ++j) {
+    const double tau = tau_s[j & 1];
+    const double* v = vbuf[j & 1];
+    const double* vrow = v + r0;
     const bool live = act && c > j;
+    double pc = 0.0, vc = 0.0;
     if (tau != 0.0) {
-      // 2. partial products with v
-      if (live) {
-        double s0 = 0.0, s1 = 0.0;
+      double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int k = 0; k < kRegRows; k += 2) {
-          s0 += x[k] * vrow[k];
-          s1 += x[k + 1] * vrow[k + 1];
-        }
-        pd[b * kTriLdsMax + c] = s0 + s1;
+      for (int k = 0; k < kRegRows; k += 2) {
+        s0 += x[k] * vrow[k];
+        s1 += x[k + 1] * vrow[k + 1];
       }
-      __syncthreads();
-      // 3. p = tau S v and the partials of p.v
-      double pc = 0.0, vc = 0.0;
+      const double sp = quad_sum(s0 + s1);
       if (live) {
-        double sp = 0.0;
-#pragma unroll
-        for (int i = 0; i < kRegBlocks; ++i) sp += pd[i * kTriLdsMax + c];
         pc = tau * sp;
-        vc = vbuf[c];
+        vc = v[c];
       }
       if (act && b == 0) pbuf[c] = pc;
       const double contrib = wave_sum((live && b == 0) ? pc * vc : 0.0);
       if (lane == 0) red[wv] = contrib;
       __syncthreads();
-      // 4. rank-2 update
       if (live) {
         double kk = 0.0;
 #pragma unroll
@@ -384,31 +394,24 @@ __global__ __launch_bounds__(kRegThreads) void k_tridiag_reg(const double* __res
         for (int k = 0; k < kRegRows; ++k) x[k] = fma(-vrow[k], g, fma(-prow[k], vc, x[k]));
       }
     }
-    if (act && c == j + 1) {
-#pragma unroll
-      for (int k = 0; k < kRegRows; ++k) crow[k] = x[k];
-    }
+    if (j + 3 < a && wv == ((j + 1) >> 4)) reflector(j + 1);
     __syncthreads();
   }
-  // the last 2 x 2 block (column a-2 is in colbuf when the loop ran)
-  if (a >= 2) {
-    if (act && c == a - 2) {
-#pragma unroll
-      for (int k = 0; k < kRegRows; ++k) crow[k] = x[k];
-    }
-    __syncthreads();
-    if (t == 0) {
-      d[a - 2] = colbuf[a - 2];
-      e[a - 2] = colbuf[a - 1];
-    }
-    __syncthreads();
-  }
+  // the last 2 x 2 block
   if (act && c == a - 1) {
 #pragma unroll
-    for (int k = 0; k < kRegRows; ++k) crow[k] = x[k];
+    for (int k = 0; k < kRegRows; ++k) colbuf[r0 + k] = x[k];
+  }
+  if (a >= 2 && act && c == a - 2) {
+#pragma unroll
+    for (int k = 0; k < kRegRows; ++k) pbuf[r0 + k] = x[k];
   }
   __syncthreads();
   if (t == 0) {
+    if (a >= 2) {
+      d[a - 2] = pbuf[a - 2];
+      e[a - 2] = pbuf[a - 1];
+    }
     d[a - 1] = colbuf[a - 1];
     e[a - 1] = 0.0;
   }
@@ -730,82 +733,73 @@ __global__ __launch_bounds__(kTriThreads) void k_mgs(int a, const double* __rest
 }
 
 // Modified Gram-Schmidt for a <= kTriLdsMax with the columns in registers
-// (RegLayout).  Step j: the owners of column j have published it (double
-// buffered) with the block partials of its squared norm; every thread forms
-// its partial product with its column, the partials of a column are summed
-// in block order, and the column is updated.  A second pass runs only when
-// some pair of columns of the first pass had |cos| > 1e-3 (below that one
-// pass already leaves them orthogonal to rounding level).  Xin is
-// [row][column], Xo column-major.
+// (RegLayout), one barrier per step: every column c > j takes its product
+// with the published column j (quad reduction) and is updated; the wavefront
+// owning column j+1 then publishes it with its squared norm (double buffered
+// by step parity).  A second pass runs only when some pair of columns of the
+// first pass had |cos| > 1e-3 (below that one pass already leaves them
+// orthogonal to rounding level).  Xin is [row][column], Xo column-major.
 __global__ __launch_bounds__(kRegThreads) void k_mgs_reg(int a, const double* __restrict__ Xin,
                                                          double* __restrict__ Xo) {
   constexpr int nw = kRegThreads / 64;
   __shared__ double qbuf[2][kPadRows];
-  __shared__ double pd[kRegBlocks * kTriLdsMax];
-  __shared__ double np[kRegBlocks];
+  __shared__ double nrm_s[2];
   __shared__ double red[nw];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const RegLayout L(a, t);
-  const int c = L.c, b = L.b, r0 = L.r0;
+  const int c = L.c, r0 = L.r0;
   const bool act = L.act;
   double x[kRegRows];
 #pragma unroll
   for (int k = 0; k < kRegRows; ++k) x[k] = (act && r0 + k < a) ? Xin[(size_t)(r0 + k) * a + c] : 0.0;
+  // publish column jj (by its whole wavefront: the quad reduction needs every
+  // lane active) and return its squared norm in the owner quad
+  auto publish = [&](int jj) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRegRows; ++k) s += x[k] * x[k];
+    s = quad_sum(s);
+    if (act && c == jj) {
+      double* qn = qbuf[jj & 1] + r0;
+#pragma unroll
+      for (int k = 0; k < kRegRows; ++k) qn[k] = x[k];
+      if (L.b == 0) nrm_s[jj & 1] = s;
+    }
+    return s;
+  };
   for (int pass = 0; pass < 2; ++pass) {
     double cmax = 0.0;  // largest |cos| between column c and an earlier column
     double cur = 0.0;   // squared norm of column c, tracked through the updates
 #pragma unroll
     for (int k = 0; k < kRegRows; ++k) cur += x[k] * x[k];
-    if (act && c == 0) {
-#pragma unroll
-      for (int k = 0; k < kRegRows; ++k) qbuf[0][r0 + k] = x[k];
-      np[b] = cur;
-    }
-    __syncthreads();
+    cur = quad_sum(cur);
     double mynorm = 0.0;
+    if (wv == 0) publish(0);
+    __syncthreads();
     for (int j = 0; j + 1 < a; ++j) {
-      double nj = 0.0;
-#pragma unroll
-      for (int i = 0; i < kRegBlocks; ++i) nj += np[i];
+      const double nj = nrm_s[j & 1];
       if (c == j) mynorm = nj;
-      const bool live = act && c > j;
       const double* q = qbuf[j & 1] + r0;
-      if (live) {
-        double s0 = 0.0, s1 = 0.0;
+      double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int k = 0; k < kRegRows; k += 2) {
-          s0 += q[k] * x[k];
-          s1 += q[k + 1] * x[k + 1];
-        }
-        pd[b * kTriLdsMax + c] = s0 + s1;
+      for (int k = 0; k < kRegRows; k += 2) {
+        s0 += q[k] * x[k];
+        s1 += q[k + 1] * x[k + 1];
       }
-      __syncthreads();
-      if (live) {
-        double dot = 0.0;
-#pragma unroll
-        for (int i = 0; i < kRegBlocks; ++i) dot += pd[i * kTriLdsMax + c];
+      const double dot = quad_sum(s0 + s1);
+      // reload q for the update instead of holding 34 more values in registers
+      asm volatile("" ::: "memory");
+      if (act && c > j) {
         const double coef = nj > 0.0 ? dot / nj : 0.0;
         if (pass == 0 && nj > 0.0 && cur > 0.0) cmax = fmax(cmax, fabs(dot) * rsqrt(nj) * rsqrt(cur));
 #pragma unroll
         for (int k = 0; k < kRegRows; ++k) x[k] = fma(-coef, q[k], x[k]);
         cur = fmax(cur - dot * coef, 0.0);
-        if (c == j + 1) {
-          double s = 0.0;
-          double* qn = qbuf[(j + 1) & 1] + r0;
-#pragma unroll
-          for (int k = 0; k < kRegRows; ++k) {
-            qn[k] = x[k];
-            s += x[k] * x[k];
-          }
-          np[b] = s;
-        }
       }
+      if (wv == ((j + 1) >> 4)) publish(j + 1);
       __syncthreads();
     }
-    double nl = 0.0;
-#pragma unroll
-    for (int i = 0; i < kRegBlocks; ++i) nl += np[i];
-    if (c == a - 1) mynorm = nl;
+    if (c == a - 1) mynorm = nrm_s[(a - 1) & 1];
     const double sc = mynorm > 0.0 ? 1.0 / sqrt(mynorm) : 0.0;
 #pragma unroll
     for (int k = 0; k < kRegRows; ++k) x[k] *= sc;
