@@ -34,7 +34,7 @@ constexpr int kTriThreads = 1024;
 constexpr int kTriLdsMax = 136;  // a^2 + 10 a doubles fit in the 160 KB of LDS
 constexpr int kBisWaves = 4;
 constexpr int kInvThreads = 64;
-constexpr int kBackWaves = 8;
+constexpr int kBackWaves = 16;
 
 void check(const char* what) {
   hipError_t e = hipGetLastError();
@@ -524,6 +524,7 @@ __device__ void invit_one(int a, const double* dd, const double* ee, double tn, 
   // factorisation, eliminating the random right-hand side on the fly; Ui
   // holds the reciprocals of the pivots
   double cd = dd[0] - l, cu = a > 1 ? ee[0] : 0.0, cb = unit_rand(seed);
+#pragma unroll 4
   for (int r = 0; r + 1 < a; ++r) {
     const double sub = ee[r];
     const double nd = dd[r + 1] - l;
@@ -565,6 +566,7 @@ __device__ void invit_one(int a, const double* dd, const double* ee, double tn, 
   for (int step = 0; step < 2; ++step) {
     if (step == 1) {
       double cbf = x[0];
+#pragma unroll 4
       for (int r = 0; r + 1 < a; ++r) {
         const int o = r * stride;
         const double nb = x[o + stride];
@@ -582,6 +584,7 @@ __device__ void invit_one(int a, const double* dd, const double* ee, double tn, 
       x[(a - 1) * stride] = cbf;
     }
     double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+#pragma unroll 4
     for (int r = a - 1; r >= 0; --r) {
       const int o = r * stride;
       const double u1 = r + 1 < a ? U1[o] : 0.0;
@@ -820,32 +823,59 @@ __global__ __launch_bounds__(kRegThreads) void k_mgs_reg(int a, const double* __
   }
 }
 
-// V = H_0 H_1 ... H_{a-3} X, one wavefront per column of X; the reflectors
-// are staged in LDS when they fit.
+// V = H_0 H_1 ... H_{a-3} X, one wavefront per column of X.  For a <=
+// kTriLdsMax the column lives in registers (three rows per lane) and the
+// reflectors are staged once per workgroup in LDS; beyond, the column is in
+// LDS and the reflectors are read from global memory.
 __global__ __launch_bounds__(64 * kBackWaves) void k_backtransform(int a, const double* __restrict__ Rg,
                                                                    const double* __restrict__ tau_g,
                                                                    const double* __restrict__ X,
                                                                    double* __restrict__ V) {
   extern __shared__ double bt[];
-  const bool in_lds = a <= kTriLdsMax;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int aa = a * a;
-  double* col = in_lds ? bt + aa + a : bt;
-  if (in_lds) {
-    for (int idx = tid; idx < aa; idx += 64 * kBackWaves) bt[idx] = Rg[idx];
-    for (int idx = tid; idx < a; idx += 64 * kBackWaves) bt[aa + idx] = tau_g[idx];
+  const int nwv = blockDim.x >> 6;
+  const int c = blockIdx.x * nwv + wv;
+  if (a <= kTriLdsMax) {
+    const int aa = a * a;
+    for (int idx = tid; idx < aa; idx += blockDim.x) bt[idx] = Rg[idx];
+    for (int idx = tid; idx < a; idx += blockDim.x) bt[aa + idx] = tau_g[idx];
     __syncthreads();
+    if (c >= a) return;  // no barrier follows
+    double x[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int r = lane + 64 * m;
+      x[m] = r < a ? X[(size_t)c * a + r] : 0.0;
+    }
+    for (int j = a - 3; j >= 0; --j) {
+      const double t = bt[aa + j];
+      if (t == 0.0) continue;
+      const double* vj = bt + (size_t)j * a;
+      double v[3], dp = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const int r = lane + 64 * m;
+        v[m] = (r > j && r < a) ? vj[r] : 0.0;
+        dp += v[m] * x[m];
+      }
+      dp = wave_sum(dp) * t;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) x[m] -= dp * v[m];
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int r = lane + 64 * m;
+      if (r < a) V[(size_t)c * a + r] = x[m];
+    }
+    return;
   }
-  const double* Rs = in_lds ? bt : Rg;
-  const double* ts = in_lds ? bt + aa : tau_g;
-  const int c = blockIdx.x * kBackWaves + wv;
-  if (c >= a) return;  // no barrier follows
-  double* x = col + (size_t)wv * a;
+  if (c >= a) return;
+  double* x = bt + (size_t)wv * a;
   for (int r = lane; r < a; r += 64) x[r] = X[(size_t)c * a + r];
   for (int j = a - 3; j >= 0; --j) {
-    const double t = ts[j];
+    const double t = tau_g[j];
     if (t == 0.0) continue;
-    const double* vj = Rs + (size_t)j * a;
+    const double* vj = Rg + (size_t)j * a;
     double dp = 0.0;
     for (int r = j + 1 + lane; r < a; r += 64) dp += vj[r] * x[r];
     dp = wave_sum(dp) * t;
@@ -894,9 +924,10 @@ void sym_eig(hipStream_t s, const double* G, int a, double* V, double* w, double
     hipLaunchKernelGGL(k_mgs, dim3(1), dim3(kTriThreads), sizeof(double) * a, s, a, X, Xo, S);
   }
   check("sym_eig mgs");
-  const size_t bt_lds = sizeof(double) * ((a <= kTriLdsMax ? aa + a : 0) + (size_t)kBackWaves * a);
-  hipLaunchKernelGGL(k_backtransform, dim3((a + kBackWaves - 1) / kBackWaves), dim3(64 * kBackWaves),
-                     bt_lds, s, a, R, tau, Xo, V);
+  // one wavefront per column; 8 per workgroup when columns live in LDS
+  const int bw = a <= kTriLdsMax ? kBackWaves : 8;
+  const size_t bt_lds = sizeof(double) * (a <= kTriLdsMax ? aa + a : (size_t)bw * a);
+  hipLaunchKernelGGL(k_backtransform, dim3((a + bw - 1) / bw), dim3(64 * bw), bt_lds, s, a, R, tau, Xo, V);
   check("sym_eig backtransform");
 }
 
