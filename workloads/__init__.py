@@ -130,3 +130,91 @@ def config_large() -> Workload:
     w = weighted_cp(512, 3, 12, 10, 3002, 3003, name="poisson_weighted12_p3_nel512_r10")
     w.eps_min = 1e-8
     return w
+
+
+# --- block (3-component) problems: linear elasticity -------------------------
+
+@dataclass
+class BlockWorkload:
+    """A 3 x 3 block system (Sec. 5.3): ``blocks[(a, b)]`` is the operator
+    recipe ``(modes, nnz)`` of block A_ab (test component a, trial component
+    b; absent = zero block), ``rhs`` the three component recipes and
+    ``prec_coef[a]`` the direction coefficients of component a's FD
+    preconditioner (Algorithm 4 with c_1 L_1 + c_2 L_2 + c_3 L_3)."""
+    name: str
+    n_el: int
+    p: int
+    blocks: dict
+    rhs: list
+    prec_coef: list
+    tol: float = 1e-6
+    eps_min: float | None = None
+    params: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.n_el + self.p - 2
+
+
+def _add_term(modes, nnz, mats, coef):
+    """Append the Kronecker term coef * mats[0] (x) mats[1] (x) mats[2] to a
+    Tucker-matrix recipe, reusing 1D matrices already listed in a mode."""
+    idx = []
+    for k in range(3):
+        if mats[k] not in modes[k]:
+            modes[k].append(mats[k])
+        idx.append(modes[k].index(mats[k]))
+    nnz.append((idx[0], idx[1], idx[2], float(coef)))
+
+
+def elasticity(n_el: int, p: int, lam: float, mu: float, rank: int, seed_op: int,
+               seed_rhs: int, S: int = 2, amp: float = 0.5, name: str | None = None) -> BlockWorkload:
+    """Compressible linear elasticity on a weighted ("deformed") cube, Dirichlet
+    on all faces: b(u, v) = int w(x) [2 mu eps(u):eps(v) + lam div u div v]
+    with w(x) = sum_{s<S} prod_k w_{s,k}(x_k), w_{s,k}(x) = 1 + amp cos(a x + b),
+    a, b ~ U[0, 2] (seed_op).  Every w_s > 0, so the operator is SPD.
+
+    Block (a, b) pairs test component a with trial component b:
+      A_aa = sum_s [(lam + 2 mu) stiff_a + mu sum_{c != a} stiff_c]  (3 S terms)
+      A_ab = sum_s [mu d_a(trial) d_b(test) + lam d_b(trial) d_a(test)]  (2 S terms)
+    where stiff_c is the stiffness matrix in direction c with masses in the
+    other directions, d_c(trial) the trial derivative in direction c
+    ("mixed01") and d_c(test) the test derivative ("mixed10").  rhs: three
+    Tucker vectors of rank `rank` with N(0, 1) core and factors
+    (seeds seed_rhs + a).  Preconditioner of component a: direction
+    coefficients lam + 2 mu in direction a and mu in the others."""
+    rng = np.random.default_rng(seed_op)
+    ab = rng.uniform(0.0, 2.0, size=(S, 3, 2))
+    wt = [[(1.0, amp, float(ab[s, k, 0]), float(ab[s, k, 1])) for k in range(3)] for s in range(S)]
+    blocks = {}
+    for a in range(3):
+        for b in range(3):
+            modes, nnz = [[], [], []], []
+            for s in range(S):
+                if a == b:
+                    for c in range(3):
+                        mats = [("stiff" if k == c else "mass", wt[s][k]) for k in range(3)]
+                        _add_term(modes, nnz, mats, (lam + 2.0 * mu) if c == a else mu)
+                else:
+                    third = 3 - a - b
+                    m_mu, m_lam = [None] * 3, [None] * 3
+                    m_mu[a], m_mu[b], m_mu[third] = ("mixed01", wt[s][a]), ("mixed10", wt[s][b]), ("mass", wt[s][third])
+                    m_lam[a], m_lam[b], m_lam[third] = ("mixed10", wt[s][a]), ("mixed01", wt[s][b]), ("mass", wt[s][third])
+                    _add_term(modes, nnz, m_mu, mu)
+                    _add_term(modes, nnz, m_lam, lam)
+            blocks[(a, b)] = (modes, nnz)
+    n = n_el + p - 2
+    rhs = [random_rhs(n, rank, seed_rhs + a) for a in range(3)]
+    coef = [[(lam + 2.0 * mu) if k == a else mu for k in range(3)] for a in range(3)]
+    return BlockWorkload(name or f"elasticity_nel{n_el}_p{p}_r{rank}", n_el, p, blocks, rhs, coef)
+
+
+def config_elasticity() -> BlockWorkload:
+    """3D linear elasticity stand-in: p = 3, n_el = 256 (259 dofs/direction),
+    Lame lambda = 1, mu = 0.5, two separable weight terms (seed 5002): 6
+    Kronecker terms in every diagonal block, 4 in every off-diagonal block;
+    rhs of rank 4 per component (seeds 5003..5005); tol 1e-6, eps_min 1e-8
+    (white-noise rhs, as for the deformed Poisson workload)."""
+    w = elasticity(256, 3, 1.0, 0.5, 4, 5002, 5003, name="elasticity_p3_nel256_r4")
+    w.eps_min = 1e-8
+    return w
