@@ -253,6 +253,27 @@ void tk_tpcg_defaults(tk_tpcg_params* p);
 tk_status tpcg_solve(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_tucker* f,
                      const tk_tpcg_params* params, tk_tucker** x, tk_tpcg_info* info);
 
+/* ---- block (3-component) systems, Sec. 5.3 (eq. block-system-elasticity) -- */
+
+/* y_a = sum_b A_ab x_b for a 3 x 3 block operator.  A is row-major (A[3a+b]
+ * is block (a, b): test component a, trial component b); a null entry is a
+ * zero block, at least one must be set.  x[3] are the components (one shape
+ * for all, matching every block); y[3] receive new lazy tensors (caller frees
+ * each with tk_tucker_free).  TK_EINVAL on null or mismatched arguments. */
+tk_status tucker_apply_op_block(tk_ctx* ctx, const tk_op* const A[9], tk_tucker* const x[3],
+                                tk_tucker* y[3]);
+
+/* Algorithm 5 on block vectors: products, sums, scalar products
+ * (<x, y> = sum_a <x_a, y_a>) and truncations (every component with the same
+ * relative tolerance, also inside Algorithm 2) act blockwise; P[a] is the
+ * preconditioner of component a (block-diagonal preconditioner, Sec. 5.3).
+ * A as for tucker_apply_op_block; f[3] the right-hand side components.  x[3]
+ * receive plain Tucker tensors; info->rank holds, per mode, the largest rank
+ * over the components.  Status as for tpcg_solve. */
+tk_status tpcg_solve_block(tk_ctx* ctx, const tk_op* const A[9], const tk_prec* const P[3],
+                           tk_tucker* const f[3], const tk_tpcg_params* params, tk_tucker* x[3],
+                           tk_tpcg_info* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -769,6 +769,164 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
   return st;
 }
 
+// ---------------------------------------------------------------------------
+// Block (3-component) systems, Sec. 5.3: products, scalar products, sums and
+// truncations act blockwise; the preconditioner is block diagonal.
+// ---------------------------------------------------------------------------
+
+// y_a = sum_b A_ab x_b (A row-major 3 x 3, null = zero block)
+static void apply_op_block(tk_ctx* ctx, const tk_op* const A[9], tk_tucker* const x[3], Owned y[3]) {
+  for (int a = 0; a < 3; ++a) {
+    Owned acc;
+    for (int b = 0; b < 3; ++b) {
+      if (!A[3 * a + b]) continue;
+      Owned t(apply_op(ctx, A[3 * a + b], x[b]));
+      acc = acc.t ? Owned(lin_comb(ctx, 1.0, acc.t, 1.0, t.t)) : std::move(t);
+    }
+    if (!acc.t) {
+      int r0[3] = {0, 0, 0};
+      acc = Owned(make_plain(ctx, x[a]->n, r0));
+    }
+    y[a] = std::move(acc);
+  }
+}
+
+static tk_status tpcg_block(tk_ctx* ctx, const tk_op* const A[9], const tk_prec* const P[3],
+                            const tk_tucker* const f_in[3], const tk_tpcg_params& prm, tk_tucker* x_out[3],
+                            tk_tpcg_info* info) {
+  tk_tpcg_info inf{};
+  const double tol = prm.tol, beta = prm.beta, alpha = prm.alpha, delta = prm.delta;
+  const double eps_min = prm.eps_min > 0 ? prm.eps_min : 0.1 * tol;
+  auto bdot = [&](Owned* x, Owned* y) {
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a) s += dot(ctx, x[a].t, y[a].t);
+    return s;
+  };
+  auto raw = [](Owned* v, tk_tucker* out[3]) {
+    for (int a = 0; a < 3; ++a) out[a] = v[a].t;
+  };
+  auto trunc = [&](Owned* y, double eps, Owned* out) {
+    for (int a = 0; a < 3; ++a) out[a] = Owned(truncate(ctx, y[a].t, eps, nullptr));
+    inf.trel_calls += 1;
+  };
+  // ||r|| of a truncated block vector (orthonormal factors per component)
+  auto tnorm = [&](Owned* r) {
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double c = core_norm(ctx, r[a].t);
+      s += c * c;
+    }
+    return std::sqrt(s);
+  };
+  double nf2 = 0.0;
+  for (int a = 0; a < 3; ++a) nf2 += dot(ctx, f_in[a], f_in[a]);
+  const double nf = std::sqrt(std::max(nf2, 0.0));
+  Owned x[3], f[3], r[3], z[3], p[3], q[3], tmp[3];
+  int r0[3] = {0, 0, 0};
+  for (int a = 0; a < 3; ++a) x[a] = Owned(make_plain(ctx, f_in[a]->n, r0));
+  if (nf == 0.0) {
+    for (int a = 0; a < 3; ++a) x_out[a] = x[a].release();
+    inf.converged = 1;
+    if (info) *info = inf;
+    return TK_OK;
+  }
+  for (int a = 0; a < 3; ++a) f[a] = Owned(scaled_copy(ctx, f_in[a], 1.0 / nf));  // ||f|| = 1
+  double nr = 1.0;
+  bool single = true;
+  for (int a = 0; a < 3; ++a) single = single && f[a].t->blocks.size() == 1;
+  if (single) {
+    for (int a = 0; a < 3; ++a) r[a] = Owned(scaled_copy(ctx, f[a].t, 1.0));  // r_0 = f
+  } else {
+    trunc(f, 0.0, r);
+    nr = tnorm(r);
+  }
+  double eta = beta * tol / nr;
+  auto precond = [&](Owned* s, Owned* out) {
+    for (int a = 0; a < 3; ++a) out[a] = Owned(apply_prec(ctx, P[a], s[a].t));
+  };
+  auto op_apply = [&](Owned* v, Owned* out) {
+    tk_tucker* vr[3];
+    raw(v, vr);
+    apply_op_block(ctx, A, vr, out);
+  };
+  precond(r, tmp);
+  trunc(tmp, eta, z);
+  for (int a = 0; a < 3; ++a) p[a] = Owned(scaled_copy(ctx, z[a].t, 1.0));
+  op_apply(p, tmp);
+  trunc(tmp, eta, q);
+  double xi = bdot(p, q);
+  double eps = prm.eps0;
+  int k = 0;
+  tk_status st = TK_OK;
+  while (nr > tol && k < prm.maxit) {
+    if (!std::isfinite(xi) || xi <= 0.0) { st = TK_EBREAKDOWN; break; }
+    const double om = bdot(r, p) / xi;
+    if (!std::isfinite(om)) { st = TK_EBREAKDOWN; break; }
+    // Algorithm 2 on the block vector y~ = x_k + om p_k, dy~ = om p_k
+    TruncPrep prep[3];
+    Owned yt[3];
+    for (int a = 0; a < 3; ++a) {
+      yt[a] = Owned(lin_comb(ctx, 1.0, x[a].t, om, p[a].t));
+      prep[a] = truncate_prepare(ctx, yt[a].t);
+    }
+    const double den = om * om * bdot(p, p);
+    const double base = om * bdot(p, x);
+    double eps_new = eps;
+    Owned x1[3];
+    while (true) {
+      for (int a = 0; a < 3; ++a) x1[a] = Owned(truncate_finish(ctx, prep[a], eps_new, nullptr));
+      ++inf.trel_calls;
+      if (den == 0.0) break;
+      const double v = (om * bdot(p, x1) - base) / den;
+      if (std::fabs(v - 1.0) < delta) break;
+      if (alpha * eps_new > eps_min) eps_new *= alpha;
+      else break;
+    }
+    eps = eps_new;
+    for (int a = 0; a < 3; ++a) {
+      x[a] = std::move(x1[a]);
+      yt[a] = Owned();
+    }
+    // r_{k+1} = T^rel(f - A x_{k+1}, eta_k)
+    op_apply(x, tmp);
+    Owned res[3];
+    for (int a = 0; a < 3; ++a) {
+      res[a] = Owned(lin_comb(ctx, 1.0, f[a].t, -1.0, tmp[a].t));
+      tmp[a] = Owned();
+    }
+    trunc(res, eta, r);
+    nr = tnorm(r);
+    ++k;
+    if (prm.verbose)
+      std::fprintf(stderr, "tpcg-block it %d relres %.3e rank (%d,%d,%d) eps %.2e\n", k, nr, x[0].t->m[0],
+                   x[0].t->m[1], x[0].t->m[2], eps);
+    if (!std::isfinite(nr)) { st = TK_EBREAKDOWN; break; }
+    if (nr <= tol) break;
+    eta = beta * tol / nr;
+    precond(r, tmp);
+    trunc(tmp, eta, z);
+    const double bk = -bdot(z, q) / xi;
+    for (int a = 0; a < 3; ++a) tmp[a] = Owned(lin_comb(ctx, 1.0, z[a].t, bk, p[a].t));
+    trunc(tmp, eta, p);
+    op_apply(p, tmp);
+    trunc(tmp, eta, q);
+    xi = bdot(p, q);
+  }
+  inf.iters = k;
+  inf.relres = nr;
+  inf.converged = nr <= tol;
+  inf.eps_final = eps;
+  if (st == TK_OK && !inf.converged) st = TK_ENOCONV;
+  for (int a = 0; a < 3; ++a) {
+    tk_tucker* xo = x[a].release();
+    for (auto& b : xo->blocks) b.c *= nf;
+    for (int kk = 0; kk < 3; ++kk) inf.rank[kk] = std::max<int64_t>(inf.rank[kk], xo->m[kk]);
+    x_out[a] = xo;
+  }
+  if (info) *info = inf;
+  return st;
+}
+
 }  // namespace tk
 
 // ===========================================================================
@@ -1197,6 +1355,56 @@ tk_status tk_sym_eig(tk_ctx* ctx, const double* G, int32_t a, double* V, double*
     gpu::sym_eig(ctx->stream, G, a, V, w, work->p);
     return TK_OK;
   });
+}
+
+// checks of a block system's arguments: three right-hand sides of one shape,
+// every nonzero block and every preconditioner of that shape
+static bool block_args_ok(const tk_op* const A[9], const tk_prec* const P[3], const tk_tucker* const v[3]) {
+  if (!A || !v) return false;
+  for (int a = 0; a < 3; ++a) {
+    if (!v[a]) return false;
+    for (int k = 0; k < 3; ++k)
+      if (v[a]->n[k] != v[0]->n[k]) return false;
+  }
+  bool any = false;
+  for (int i = 0; i < 9; ++i) {
+    if (!A[i]) continue;
+    any = true;
+    for (int k = 0; k < 3; ++k)
+      if (A[i]->n[k] != v[0]->n[k]) return false;
+  }
+  if (!any) return false;
+  if (P) {
+    for (int a = 0; a < 3; ++a) {
+      if (!P[a]) return false;
+      for (int k = 0; k < 3; ++k)
+        if (P[a]->dir[k].n != v[0]->n[k]) return false;
+    }
+  }
+  return true;
+}
+
+tk_status tucker_apply_op_block(tk_ctx* ctx, const tk_op* const A[9], tk_tucker* const x[3], tk_tucker* y[3]) {
+  if (!ctx || !y || !block_args_ok(A, nullptr, x)) return TK_EINVAL;
+  return guarded(ctx, [&]() {
+    Owned out[3];
+    apply_op_block(ctx, A, x, out);
+    for (int a = 0; a < 3; ++a) y[a] = out[a].release();
+    return TK_OK;
+  });
+}
+
+tk_status tpcg_solve_block(tk_ctx* ctx, const tk_op* const A[9], const tk_prec* const P[3],
+                           tk_tucker* const f[3], const tk_tpcg_params* params, tk_tucker* x[3],
+                           tk_tpcg_info* info) {
+  if (!ctx || !x || !P || !block_args_ok(A, P, f)) return TK_EINVAL;
+  tk_tpcg_params prm;
+  tk_tpcg_defaults(&prm);
+  if (params) prm = *params;
+  if (!(prm.tol > 0) || !(prm.alpha > 0 && prm.alpha < 1) || !(prm.eps0 > 0) || prm.maxit < 1)
+    return TK_EINVAL;
+  for (int a = 0; a < 3; ++a) x[a] = nullptr;
+  return guarded(ctx, [&]() { return tpcg_block(ctx, A, P, f, prm, x, info); });
 }
 
 tk_status tk_dgemm(tk_ctx* ctx, int32_t ta, int32_t tb, int32_t M, int32_t N, int32_t K, double alpha,

@@ -30,3 +30,26 @@ def rhs(ctx, w) -> tk.Tucker:
 
 def preconditioner(ctx, w, eps_prec=0.1, coef=(1.0, 1.0, 1.0)) -> tk.Preconditioner:
     return tk.Preconditioner.create(ctx, w.n_el, w.p, eps_prec, coef)
+
+
+# --- block (3-component) systems --------------------------------------------
+
+def block_operator(ctx, bw) -> list:
+    """3 x 3 nested list of Operator (None for a zero block) of a BlockWorkload."""
+    ops = [[None] * 3 for _ in range(3)]
+    for (a, b), (modes, nnz) in bw.blocks.items():
+        bands = [np.stack([tk.assemble_1d(bw.n_el, bw.p, kind, weight) for kind, weight in modes[k]])
+                 for k in range(3)]
+        ops[a][b] = tk.Operator.create(ctx, bw.p, (bw.n,) * 3, bands, nnz)
+    return ops
+
+
+def block_rhs(ctx, bw) -> list:
+    return [tk.Tucker.from_host(ctx, np.asarray(spec["core"]), [np.asarray(u) for u in spec["factors"]])
+            for spec in bw.rhs]
+
+
+def block_preconditioner(ctx, bw, eps_prec=0.1) -> list:
+    """Block-diagonal preconditioner: one FD per component with its direction
+    coefficients."""
+    return [tk.Preconditioner.create(ctx, bw.n_el, bw.p, eps_prec, bw.prec_coef[a]) for a in range(3)]

@@ -73,6 +73,9 @@ EXPORTS = {
     "tucker_truncate": (C.c_int32, [vp, vp, C.c_double, C.POINTER(vp), dp]),
     "tk_tpcg_defaults": (None, [C.POINTER(TpcgParams)]),
     "tk_sym_eig": (C.c_int32, [vp, vp, C.c_int32, vp, vp]),
+    "tucker_apply_op_block": (C.c_int32, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]),
+    "tpcg_solve_block": (C.c_int32, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                     C.POINTER(TpcgParams), C.POINTER(vp), C.POINTER(TpcgInfo)]),
     "tk_dgemm": (C.c_int32, [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                              vp, C.c_int32, vp, C.c_int32, C.c_double, vp, C.c_int32]),
     "tk_prof_enable": (C.c_int32, [vp, C.c_int32]),
@@ -411,6 +414,36 @@ def sym_eig(ctx, G_dev, a: int, V_dev, w_dev) -> None:
             raise ValueError("sym_eig needs contiguous float64 device tensors of the right size")
     ctx.check(lib().tk_sym_eig(ctx.h, vp(G_dev.data_ptr()), a, vp(V_dev.data_ptr()),
                                vp(w_dev.data_ptr())), "tk_sym_eig")
+
+
+def _block_ops(ops):
+    """3 x 3 nested list of Operator (or None for a zero block) -> void*[9]."""
+    return (vp * 9)(*[(ops[a][b].h if ops[a][b] is not None else None) for a in range(3) for b in range(3)])
+
+
+def tucker_apply_op_block(ctx, ops, x) -> list:
+    """y_a = sum_b A_ab x_b; ops is a 3 x 3 nested list (None = zero block)."""
+    out = (vp * 3)()
+    ctx.check(lib().tucker_apply_op_block(ctx.h, _block_ops(ops), (vp * 3)(*[t.h for t in x]), out),
+              "tucker_apply_op_block")
+    return [Tucker(ctx, out[a]) for a in range(3)]
+
+
+def tpcg_solve_block(ctx, ops, precs, f, allow_noconv=False, **params):
+    """Algorithm 5 on a 3-component block system (Sec. 5.3); returns
+    ([x_1, x_2, x_3], info)."""
+    prm = tpcg_params(**params)
+    info = TpcgInfo()
+    out = (vp * 3)()
+    st = lib().tpcg_solve_block(ctx.h, _block_ops(ops), (vp * 3)(*[P.h for P in precs]),
+                                (vp * 3)(*[t.h for t in f]), C.byref(prm), out, C.byref(info))
+    x = [Tucker(ctx, out[a]) if out[a] else None for a in range(3)]
+    if st != TK_OK and not (allow_noconv and st == TK_ENOCONV):
+        msg = lib().tk_last_error(ctx.h)
+        raise TkError(st, f"tpcg_solve_block: {msg.decode() if msg else ''}")
+    return x, {"iters": info.iters, "converged": bool(info.converged), "relres": info.relres,
+               "rank": tuple(info.rank), "eps_final": info.eps_final, "trel_calls": info.trel_calls,
+               "status": st}
 
 
 def dgemm(ctx, ta: bool, tb: bool, M: int, N: int, K: int, alpha: float, A_dev, lda: int,
