@@ -42,13 +42,27 @@ void householder_qr(hipStream_t s, const QrJob* jobs, int njobs);
 size_t sym_eig_work(int a);
 void sym_eig(hipStream_t s, const double* G, int a, double* V, double* w, double* work);
 
+// Several device-to-device copies (dst[0..n) = src[0..n) each) in one launch.
+constexpr int kMaxSegs = 6;
+struct CopySeg {
+  double* dst;
+  const double* src;
+  long long n;
+};
+struct CopySegs {
+  CopySeg s[kMaxSegs];
+  int n = 0;
+};
+void copy_segments(hipStream_t s, const CopySegs& cs);
+
 // e[j] = sum_i P[i, j]^2 for the a columns of P (rows x a, ld rows)
 void column_energy(hipStream_t s, const double* P, int rows, int a, double* e);
 
 // Rank choice of one ST-HOSVD mode: sort energies descending, keep the
 // smallest s whose discarded tail is <= budget, where budget =
 // eps^2 * norm2 / 3 and norm2 = *norm2_io (if set_norm, norm2 is first set to
-// sum(e)).  Writes sel[0] = s, sel[1..s] = order; tail energy to *disc.
+// sum(e)).  Writes sel[0] = s, sel[1..s] = order; tail energy to disc[0] and
+// s (as a double) to disc[1].
 void select_rank(hipStream_t s, const double* e, int a, double eps, double* norm2_io,
                  int set_norm, int* sel, double* disc);
 

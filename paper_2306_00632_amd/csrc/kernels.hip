@@ -20,6 +20,7 @@
 //                 even p).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <stdexcept>
 #include <string>
@@ -488,7 +489,8 @@ __global__ __launch_bounds__(1024) void k_select(const double* __restrict__ e, i
       else break;
     }
     sel[0] = s;
-    *disc = tail;
+    disc[0] = tail;
+    disc[1] = (double)s;  // the rank again, beside the tail, for a single readback
   }
   __syncthreads();
   const int s = sel[0];
@@ -554,6 +556,23 @@ void dot_accumulate(hipStream_t s, const double* x, const double* y, long long n
   hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, s, x, y, n, part);
   hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, part, nb, coef, out);
   check_launch("dot_accumulate");
+}
+
+// up to kMaxSegs independent device copies in one launch
+__global__ __launch_bounds__(256) void k_copy_segments(CopySegs cs) {
+  for (int i = 0; i < cs.n; ++i) {
+    const CopySeg g = cs.s[i];
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < g.n; e += 256LL * gridDim.x) g.dst[e] = g.src[e];
+  }
+}
+
+void copy_segments(hipStream_t s, const CopySegs& cs) {
+  long long mx = 0;
+  for (int i = 0; i < cs.n; ++i) mx = std::max(mx, cs.s[i].n);
+  if (mx == 0) return;
+  const int nb = (int)std::min<long long>(1024, (mx + 255) / 256);
+  hipLaunchKernelGGL(k_copy_segments, dim3(nb), dim3(256), 0, s, cs);
+  check_launch("copy_segments");
 }
 
 __global__ void k_fill(double* x, long long n, double v) {

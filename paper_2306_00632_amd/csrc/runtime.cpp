@@ -117,6 +117,7 @@ struct tk_ctx {
   std::string last_error;
   tk::BufP scal;  // device scalars: [0] accumulator + 256 scratch, [300..] misc
   tk::BufP sel;   // rank-selection output (ints)
+  double* stage = nullptr;  // pinned host staging for scalar readbacks (kStage doubles)
   // instrumentation (off by default)
   bool prof = false;
   std::vector<tk::ProfRec> recs;
@@ -184,11 +185,17 @@ static void h2d(tk_ctx* ctx, double* dst, const double* src, size_t count) {
   }
 }
 
+constexpr size_t kStage = 64;  // doubles of pinned staging per context
+
+// Device -> host copy that synchronises; small reads go through the
+// context's pinned staging buffer (one DMA, no pageable-memory staging).
 static std::vector<double> d2h(tk_ctx* ctx, const double* src, size_t count) {
   std::vector<double> out(count);
   if (count) {
-    HIPCHK(hipMemcpyAsync(out.data(), src, count * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    double* dst = (count <= kStage && ctx->stage) ? ctx->stage : out.data();
+    HIPCHK(hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     sync(ctx);
+    if (dst != out.data()) std::memcpy(out.data(), dst, count * sizeof(double));
   }
   return out;
 }
@@ -306,13 +313,16 @@ static tk_tucker* lin_comb(tk_ctx* ctx, double a, const tk_tucker* x, double b, 
   for (int k = 0; k < 3; ++k)
     if (x->n[k] != y->n[k]) throw Error(TK_EINVAL, "sum of Tucker tensors of different sizes");
   auto* t = new tk_tucker;
+  gpu::CopySegs cs;  // the six factor copies of the concatenation, one launch
   for (int k = 0; k < 3; ++k) {
     t->n[k] = x->n[k];
     t->m[k] = x->m[k] + y->m[k];
     t->U[k] = alloc(ctx, (size_t)t->n[k] * t->m[k]);
-    d2d(ctx, t->U[k]->p, x->U[k]->p, (size_t)x->n[k] * x->m[k]);
-    d2d(ctx, t->U[k]->p + (size_t)x->n[k] * x->m[k], y->U[k]->p, (size_t)y->n[k] * y->m[k]);
+    const long long nx = (long long)x->n[k] * x->m[k], ny = (long long)y->n[k] * y->m[k];
+    if (nx) cs.s[cs.n++] = gpu::CopySeg{t->U[k]->p, x->U[k]->p, nx};
+    if (ny) cs.s[cs.n++] = gpu::CopySeg{t->U[k]->p + nx, y->U[k]->p, ny};
   }
+  gpu::copy_segments(ctx->stream, cs);
   for (const auto& bl : x->blocks) {
     Block c = bl;
     c.c *= a;
@@ -508,12 +518,11 @@ static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double*
       gpu::column_energy(ctx->stream, Pm->p, bc, a, e->p);
       gpu::select_rank(ctx->stream, e->p, a, eps, norm2, k == 0 ? 1 : 0, sel, disc);
     }
-    int hsel = 0;
-    double hdisc = 0.0;
-    HIPCHK(hipMemcpyAsync(&hsel, sel, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipMemcpyAsync(&hdisc, disc, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    if (k == 0) HIPCHK(hipMemcpyAsync(&P.norm2, norm2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    sync(ctx);
+    // one readback of [norm2, tail, s] (scal + 300 .. 302)
+    const auto hv = d2h(ctx, norm2, 3);
+    if (k == 0) P.norm2 = hv[0];
+    const double hdisc = hv[1];
+    const int hsel = (int)hv[2];
     disc_total += hdisc;
     const int s = hsel;
     s_k[k] = s;
@@ -967,6 +976,7 @@ tk_status tk_ctx_create(int device, void* hip_stream, tk_ctx** out) {
   tk_status st = guarded(c, [&]() {
     c->scal = alloc(c, 512);
     c->sel = alloc(c, 1100);  // 2200 ints
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->stage), kStage * sizeof(double), hipHostMallocDefault));
     return TK_OK;
   });
   if (st != TK_OK) {
@@ -988,6 +998,7 @@ void tk_ctx_destroy(tk_ctx* ctx) {
   for (auto e : ctx->evpool) (void)hipEventDestroy(e);
   ctx->scal.reset();
   ctx->sel.reset();
+  if (ctx->stage) (void)hipHostFree(ctx->stage);
   delete ctx;
 }
 
