@@ -369,15 +369,15 @@ __global__ __launch_bounds__(kRegThreads) void k_tridiag_reg(const double* __res
     const bool live = act && c > j;
     double pc = 0.0, vc = 0.0;
     if (tau != 0.0) {
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int k = 0; k < kRegRows; k += 2) {
-        s0 += x[k] * vrow[k];
-        s1 += x[k + 1] * vrow[k + 1];
-      }
-      const double sp = quad_sum(s0 + s1);
+      // finished columns (c <= j; quads are uniform in c) skip the product
       if (live) {
-        pc = tau * sp;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRegRows; k += 2) {
+          s0 += x[k] * vrow[k];
+          s1 += x[k + 1] * vrow[k + 1];
+        }
+        pc = tau * quad_sum(s0 + s1);
         vc = v[c];
       }
       if (act && b == 0) pbuf[c] = pc;
@@ -783,13 +783,17 @@ __global__ __launch_bounds__(kRegThreads) void k_mgs_reg(int a, const double* __
       const double nj = nrm_s[j & 1];
       if (c == j) mynorm = nj;
       const double* q = qbuf[j & 1] + r0;
-      double s0 = 0.0, s1 = 0.0;
+      // columns c <= j are finished: their quads (uniform in c) skip the step
+      double dot = 0.0;
+      if (act && c > j) {
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-      for (int k = 0; k < kRegRows; k += 2) {
-        s0 += q[k] * x[k];
-        s1 += q[k + 1] * x[k + 1];
+        for (int k = 0; k < kRegRows; k += 2) {
+          s0 += q[k] * x[k];
+          s1 += q[k + 1] * x[k + 1];
+        }
+        dot = quad_sum(s0 + s1);
       }
-      const double dot = quad_sum(s0 + s1);
       // reload q for the update instead of holding 34 more values in registers
       asm volatile("" ::: "memory");
       if (act && c > j) {
