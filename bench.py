@@ -17,6 +17,9 @@ Prints one JSON line (see the "metric" key) with:
                        every launch slow the host, so the timed solves run
                        without them)
   roofline             the dominant kernel family against its MI355X peak
+  mode_products_hbm    batched standalone runs of the two HBM-bound mode-product
+                       kernels (banded operator, FD chain) moving several GB
+                       per launch: algorithmic GB/s and fraction of 8 TB/s
   cpu_baseline         the FP64 oracle on the host cores (bounded sample)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload deformed|small]
@@ -63,6 +66,86 @@ def workload(name):
     return {"deformed": W.config_deformed, "small": W.config_small, "large": W.config_large}[name]()
 
 
+# Batched standalone mode-product runs.  A single solve moves too few bytes per
+# launch to show HBM bandwidth, so each kernel family is driven through its
+# C-ABI call on one tall factor: x of ranks (m, 1, 1), m independent columns.
+K1_SHAPE = dict(n_el=1024, p=2, R=9, m=40000, seed_op=8101, seed_x=8102)
+K2_SHAPE = dict(n_el=1024, p=3, m=25600, seed_x=8202)
+
+
+def k1_inputs(shape=K1_SHAPE):
+    import workloads as W
+    w = W.weighted_cp(shape["n_el"], shape["p"], shape["R"], 1, shape["seed_op"], shape["seed_op"] + 1)
+    core, U = W.random_tucker(w.n, (shape["m"], 1, 1), shape["seed_x"])
+    return w, core, U
+
+
+def k2_inputs(shape=K2_SHAPE):
+    import workloads as W
+    n = shape["n_el"] + shape["p"] - 2
+    core, U = W.random_tucker(n, (shape["m"], 1, 1), shape["seed_x"])
+    return core, U
+
+
+def mode_products_hbm(ctx, reps=5):
+    """Algorithmic GB/s of the banded operator (tucker_apply_op) and of the
+    FD chain (fd_precond) on batched inputs.  Bytes follow the unfused
+    per-unit definitions: operator, per mode, 8 (n r + R (2p+1) n + R n r);
+    FD, per mode, 8 (n r + R_P n r + n n2) (the intermediate Z between the
+    forward and the backward transform is not counted).  Times are the
+    kernels' own (HIP events on the library's stream), summed over all
+    launches of the family, the two one-column modes included."""
+    from paper_2306_00632_amd import problem, tk
+    out = {}
+    w, core, U = k1_inputs()
+    op = problem.operator(ctx, w)
+    x = tk.Tucker.from_host(ctx, core, U)
+    del U
+    y = tk.tucker_apply_op(ctx, op, x)   # warm-up
+    del y
+    ctx.sync()
+    ctx.prof(True)
+    for _ in range(reps):
+        y = tk.tucker_apply_op(ctx, op, x)
+        del y
+    ctx.sync()
+    k = ctx.prof_read()["band_apply"]
+    ctx.prof(False)
+    del x, op
+    gbs = k["bytes"] / (k["ms"] / 1e3) / 1e9
+    out["band_apply"] = {"call": "tucker_apply_op", "n_el": w.n_el, "p": w.p, "n": w.n, "R": len(w.nnz),
+                         "ranks": [K1_SHAPE["m"], 1, 1], "GB_per_call": k["bytes"] / reps / 1e9,
+                         "ms_per_call": k["ms"] / reps, "GB_s": gbs, "frac": gbs / PEAK_HBM_GBS}
+    core, U = k2_inputs()
+    P = tk.Preconditioner.create(ctx, K2_SHAPE["n_el"], K2_SHAPE["p"], 0.1)
+    info = P.info()
+    n2 = P.direction(0)["n2"]
+    s = tk.Tucker.from_host(ctx, core, U)
+    n = U[0].shape[0]
+    del U
+    z = tk.fd_precond(ctx, P, s)   # warm-up
+    del z
+    ctx.sync()
+    ctx.prof(True)
+    for _ in range(reps):
+        z = tk.fd_precond(ctx, P, s)
+        del z
+    ctx.sync()
+    kk = ctx.prof_read()
+    ctx.prof(False)
+    del s, P
+    Rp = info["R_P"]
+    cols = K2_SHAPE["m"] + 2
+    by = 8.0 * ((1 + Rp) * n * cols + 3 * n * n2)
+    ms = kk["fd_forward"]["ms"] + kk["fd_backward"]["ms"]
+    gbs = by * reps / (ms / 1e3) / 1e9
+    out["fd_chain"] = {"call": "fd_precond", "n_el": K2_SHAPE["n_el"], "p": K2_SHAPE["p"], "n": n, "R_P": Rp,
+                       "ranks": [K2_SHAPE["m"], 1, 1], "GB_per_call": by / 1e9, "ms_per_call": ms / reps,
+                       "ms_forward": kk["fd_forward"]["ms"] / reps, "ms_backward": kk["fd_backward"]["ms"] / reps,
+                       "GB_s": gbs, "frac": gbs / PEAK_HBM_GBS}
+    return out
+
+
 def cpu_baseline(w, gpu_iters, target_s=12.0):
     """The oracle's TPCG (unchanged) on a bounded sample of the same solve:
     the first k TPCG iterations (including the initial preconditioner and
@@ -101,6 +184,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="deformed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the batched mode-product bandwidth runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of MIB MiB (read + write) before the solves, "
                          "as the known-size reference of a rocprofv3 FETCH_SIZE/WRITE_SIZE run")
@@ -209,6 +293,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if not args.no_hbm:
+        out["mode_products_hbm"] = mode_products_hbm(ctx)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline(w, last_info["iters"])
     print(json.dumps(out), flush=True)

@@ -138,7 +138,8 @@ typedef struct { int32_t i1, i2, i3; double c; } tk_core_nz;
 /* Tucker matrix sum_nz c * A_(3,i3) x A_(2,i2) x A_(1,i1).  bands[k] (host)
  * holds nmat[k] banded n[k] x n[k] matrices of half-bandwidth p in the DIA
  * layout of tk_assemble_1d, matrix t at bands[k] + t*(2p+1)*n[k].  The data
- * are copied to the device.  EINVAL on out-of-range indices. */
+ * are copied to the device.  EINVAL on out-of-range indices or p outside
+ * [0, 6] (the banded kernels hold a row's 2p + 1 entries in registers). */
 tk_status tk_op_create(tk_ctx* ctx, int32_t p, const int64_t n[3], const int32_t nmat[3],
                        const double* const bands[3], const tk_core_nz* nz, int64_t nnz,
                        tk_op** out);

@@ -79,14 +79,20 @@ void scale_copy(hipStream_t s, const double* x, long long n, double a, double* y
 // Low-rank FD transform of one direction (see setup_fd.cpp).
 struct FdDev {
   int n, n1, n2, N, odd, ke, ket, R;
+  // rows [e_lo, e_hi) of E hold a single 1 at column row + e_sh; rows
+  // [et_lo, et_hi) of E^T a single 1 at column row + et_sh; the others use
+  // the ELL tables
+  int e_lo, e_hi, e_sh, et_lo, et_hi, et_sh;
   const double* g;       // n1
   const int* e_idx;      // n * ke
   const double* e_val;
   const int* et_idx;     // n1 * ket
   const double* et_val;
   const double* v2u2;    // n x n2
-  const double* expD;    // R x n: exp(-alpha_j lam_m / lam_min)
-  const double2* tw;     // 2N/2 twiddles exp(-2 pi i t / 2N)
+  const double* ge;      // R x n: exp(-alpha_j lam_m / lam_min), times g_m for m < n1
+  const double2* cs;     // N: exp(-2 pi i x / N)
+  const double* sn;      // N: sin(pi x / N)
+  const double2* tq;     // N/2 + 1: exp(-i pi x / (2N))
 };
 // Z (n x r) = U~^T S (n x r, ld lds)
 void fd_forward(hipStream_t s, const FdDev& d, const double* S, int lds, int r, double* Z);

@@ -157,7 +157,7 @@ struct tk_prec {
   double lam_min = 0, lam_max = 0, err = 0, err_prev = 0;
   std::vector<double> alpha, omega;
   tk::FdDirection dir[3];
-  tk::BufP g[3], e_val[3], et_val[3], v2u2[3], expD[3], tw[3];
+  tk::BufP g[3], e_val[3], et_val[3], v2u2[3], ge[3], cs[3], sn[3], tq[3];
   tk::BufP e_idx[3], et_idx[3];  // stored as ints inside double buffers
   tk::gpu::FdDev dev[3];
 };
@@ -629,17 +629,17 @@ static tk_tucker* apply_prec(tk_ctx* ctx, const tk_prec* P, const tk_tucker* s) 
     if (r == 0) continue;
     BufP Z = alloc(ctx, (size_t)n * r);
     const auto& d = P->dev[k];
-    const double L = 2.0 * d.N, lg = std::log2(L);
+    // one complex FFT of length N/2 per transform plus O(N) pre- and post-processing
+    const double M = 0.5 * d.N, fft = 5.0 * M * std::log2(std::max(M, 2.0)) + 12.0 * d.N;
     {
       // algorithmic bytes: read S, write Z, boundary map and V2U2 columns
-      Prof pr(ctx, PK_FD_FWD, 8.0 * (2.0 * n * r + (double)n * d.n2),
-              r * (5.0 * L * lg + 2.0 * n * (d.ket + d.n2)));
+      Prof pr(ctx, PK_FD_FWD, 8.0 * (2.0 * n * r + (double)n * d.n2), r * (fft + 2.0 * n * (1 + d.n2)));
       gpu::fd_forward(ctx->stream, d, s->U[k]->p, n, r, Z->p);
     }
     {
       // read Z and the exp table, write R_P r columns
       Prof pr(ctx, PK_FD_BWD, 8.0 * ((double)n * r + (double)P->R * n + (double)P->R * n * r + (double)n * d.n2),
-              (double)P->R * r * (5.0 * L * lg + 2.0 * n * (d.ke + d.n2) + 3.0 * n));
+              (double)P->R * r * (fft + n * (1.0 + 2.0 * d.n2)));
       gpu::fd_backward(ctx->stream, d, Z->p, r, t->U[k]->p);
     }
   }
@@ -1166,7 +1166,7 @@ tk_status tk_tucker_axpby(tk_ctx* ctx, double a, const tk_tucker* x, double b, c
 
 tk_status tk_op_create(tk_ctx* ctx, int32_t p, const int64_t n[3], const int32_t nmat[3],
                        const double* const bands[3], const tk_core_nz* nz, int64_t nnz, tk_op** out) {
-  if (!ctx || !n || !nmat || !bands || !out || (nnz > 0 && !nz) || nnz < 0 || p < 0) return TK_EINVAL;
+  if (!ctx || !n || !nmat || !bands || !out || (nnz > 0 && !nz) || nnz < 0 || p < 0 || p > 6) return TK_EINVAL;
   *out = nullptr;
   return guarded(ctx, [&]() {
     std::unique_ptr<tk_op> op(new tk_op);
@@ -1198,6 +1198,28 @@ tk_status tucker_apply_op(tk_ctx* ctx, const tk_op* op, const tk_tucker* x, tk_t
   return guarded(ctx, [&]() { *y = apply_op(ctx, op, x); return TK_OK; });
 }
 
+// The widest range [lo, hi) of rows around the middle of an ELL matrix whose
+// rows hold exactly one entry, equal to 1, at column row + sh (sh taken from
+// the middle row); lo = hi = 0 when the middle row is not of that kind.
+static void interior_rows(const std::vector<int>& idx, const std::vector<double>& val, int k, int rows, int& lo,
+                          int& hi, int& sh) {
+  auto unit = [&](int i, int s) {
+    if (idx[(size_t)i * k] != i + s || val[(size_t)i * k] != 1.0) return false;
+    for (int t = 1; t < k; ++t)
+      if (idx[(size_t)i * k + t] >= 0) return false;
+    return true;
+  };
+  lo = hi = sh = 0;
+  const int mid = rows / 2;
+  if (rows == 0 || idx[(size_t)mid * k] < 0) return;
+  sh = idx[(size_t)mid * k] - mid;
+  if (!unit(mid, sh)) { sh = 0; return; }
+  lo = mid;
+  hi = mid + 1;
+  while (lo > 0 && unit(lo - 1, sh)) --lo;
+  while (hi < rows && unit(hi, sh)) ++hi;
+}
+
 tk_status fd_setup(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec, const double coef[3],
                    tk_prec** out, int32_t* R_P) {
   if (!ctx || !n_el || !out || !(eps_prec > 0.0)) return TK_EINVAL;
@@ -1226,13 +1248,20 @@ tk_status fd_setup(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_pre
     const double pi = 3.14159265358979323846;
     for (int k = 0; k < 3; ++k) {
       const auto& d = P->dir[k];
-      std::vector<double> expD((size_t)P->R * d.n);
+      // exp(-alpha_j lam_m / lam_min), with g_m folded in on the sine part
+      std::vector<double> ge((size_t)P->R * d.n);
       for (int j = 0; j < P->R; ++j)
-        for (int m = 0; m < d.n; ++m) expD[(size_t)j * d.n + m] = std::exp(-P->alpha[j] * d.lam[m] / P->lam_min);
-      std::vector<double> tw(2 * (size_t)d.N);
+        for (int m = 0; m < d.n; ++m)
+          ge[(size_t)j * d.n + m] = std::exp(-P->alpha[j] * d.lam[m] / P->lam_min) * (m < d.n1 ? d.g[m] : 1.0);
+      std::vector<double> cs(2 * (size_t)d.N), sn(d.N), tq(2 * (size_t)(d.N / 2 + 1));
       for (int t = 0; t < d.N; ++t) {
-        tw[2 * t] = std::cos(2.0 * pi * t / (2.0 * d.N));
-        tw[2 * t + 1] = -std::sin(2.0 * pi * t / (2.0 * d.N));
+        cs[2 * t] = std::cos(2.0 * pi * t / d.N);
+        cs[2 * t + 1] = -std::sin(2.0 * pi * t / d.N);
+        sn[t] = std::sin(pi * t / d.N);
+      }
+      for (int t = 0; t <= d.N / 2; ++t) {
+        tq[2 * t] = std::cos(pi * t / (2.0 * d.N));
+        tq[2 * t + 1] = -std::sin(pi * t / (2.0 * d.N));
       }
       auto up = [&](const std::vector<double>& v) {
         BufP b = alloc(ctx, v.size());
@@ -1251,8 +1280,10 @@ tk_status fd_setup(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_pre
       P->e_val[k] = up(d.e_val);
       P->et_val[k] = up(d.et_val);
       P->v2u2[k] = up(d.v2u2);
-      P->expD[k] = up(expD);
-      P->tw[k] = up(tw);
+      P->ge[k] = up(ge);
+      P->cs[k] = up(cs);
+      P->sn[k] = up(sn);
+      P->tq[k] = up(tq);
       P->e_idx[k] = up_int(d.e_idx);
       P->et_idx[k] = up_int(d.et_idx);
       gpu::FdDev& dv = P->dev[k];
@@ -1270,8 +1301,12 @@ tk_status fd_setup(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_pre
       dv.et_idx = reinterpret_cast<const int*>(P->et_idx[k]->p);
       dv.et_val = P->et_val[k]->p;
       dv.v2u2 = P->v2u2[k]->p;
-      dv.expD = P->expD[k]->p;
-      dv.tw = reinterpret_cast<const double2*>(P->tw[k]->p);
+      dv.ge = P->ge[k]->p;
+      dv.cs = reinterpret_cast<const double2*>(P->cs[k]->p);
+      dv.sn = P->sn[k]->p;
+      dv.tq = reinterpret_cast<const double2*>(P->tq[k]->p);
+      interior_rows(d.e_idx, d.e_val, d.ke, d.n, dv.e_lo, dv.e_hi, dv.e_sh);
+      interior_rows(d.et_idx, d.et_val, d.ket, d.n1, dv.et_lo, dv.et_hi, dv.et_sh);
     }
     if (R_P) *R_P = P->R;
     *out = P.release();

@@ -53,7 +53,9 @@ def upload(ctx, x: T.Tucker):
 
 # --- operator application (eq. tt_product) -------------------------------------
 
-@pytest.mark.parametrize("n_el,p,R,r", [(12, 3, 4, (3, 4, 2)), (128, 3, 9, (5, 7, 6)), (16, 2, 3, (1, 1, 1))])
+@pytest.mark.parametrize("n_el,p,R,r", [(12, 3, 4, (3, 4, 2)), (128, 3, 9, (5, 7, 6)), (16, 2, 3, (1, 1, 1)),
+                                        (300, 2, 9, (19, 9, 8)), (40, 5, 6, (17, 3, 11)),
+                                        (24, 6, 4, (9, 2, 10))])
 def test_apply_op(ctx, n_el, p, R, r):
     tk, prob = lib_modules()
     say(f"apply_op n_el={n_el} p={p} R={R} r={r}")
