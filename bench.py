@@ -19,7 +19,11 @@ Prints one JSON line (see the "metric" key) with:
   roofline             the dominant kernel family against its MI355X peak
   mode_products_hbm    batched standalone runs of the two HBM-bound mode-product
                        kernels (banded operator, FD chain) moving several GB
-                       per launch: algorithmic GB/s and fraction of 8 TB/s
+                       per launch: algorithmic GB/s, fraction of 8 TB/s and of a
+                       plain device copy measured in the same run, and the
+                       HBM bytes of the big launch from the committed
+                       FETCH_SIZE / WRITE_SIZE summary (null once the kernel
+                       source has changed since it was taken)
   cpu_baseline         the FP64 oracle on the host cores (bounded sample)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload deformed|small]
@@ -40,7 +44,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 # source file holding the kernels of each instrumented family
 FAMILY_SOURCE = {"sym_eig": "eig.hip", "dgemm": "kernels.hip", "band_apply": "kernels.hip",
                  "select_rank": "kernels.hip", "fd_forward": "kernels.hip", "fd_backward": "kernels.hip",
-                 "householder_qr": "kernels.hip"}
+                 "householder_qr": "kernels.hip", "band_apply_batched": "kernels.hip",
+                 "fd_forward_batched": "kernels.hip", "fd_backward_batched": "kernels.hip"}
 
 
 def measured_traffic(family):
@@ -95,8 +100,22 @@ def mode_products_hbm(ctx, reps=5):
     forward and the backward transform is not counted).  Times are the
     kernels' own (HIP events on the library's stream), summed over all
     launches of the family, the two one-column modes included."""
+    import torch
     from paper_2306_00632_amd import problem, tk
     out = {}
+    # reference: a plain device copy of 2 GiB (read + write), torch's copy kernel
+    src = torch.empty(1 << 28, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * src.numel() * 8 * reps / (ev0.elapsed_time(ev1) / 1e3) / 1e9
+    del src, dst
+    out["copy_probe"] = {"bytes_per_copy": 2 * (1 << 28) * 8, "GB_s": copy_gbs, "frac": copy_gbs / PEAK_HBM_GBS}
     w, core, U = k1_inputs()
     op = problem.operator(ctx, w)
     x = tk.Tucker.from_host(ctx, core, U)
@@ -113,9 +132,12 @@ def mode_products_hbm(ctx, reps=5):
     ctx.prof(False)
     del x, op
     gbs = k["bytes"] / (k["ms"] / 1e3) / 1e9
+    tr = measured_traffic("band_apply_batched")
     out["band_apply"] = {"call": "tucker_apply_op", "n_el": w.n_el, "p": w.p, "n": w.n, "R": len(w.nnz),
                          "ranks": [K1_SHAPE["m"], 1, 1], "GB_per_call": k["bytes"] / reps / 1e9,
-                         "ms_per_call": k["ms"] / reps, "GB_s": gbs, "frac": gbs / PEAK_HBM_GBS}
+                         "ms_per_call": k["ms"] / reps, "GB_s": gbs, "frac": gbs / PEAK_HBM_GBS,
+                         "frac_of_copy": gbs / copy_gbs,
+                         "traffic_GB_big_launch": None if tr is None else tr / 1e9}
     core, U = k2_inputs()
     P = tk.Preconditioner.create(ctx, K2_SHAPE["n_el"], K2_SHAPE["p"], 0.1)
     info = P.info()
@@ -142,7 +164,9 @@ def mode_products_hbm(ctx, reps=5):
     out["fd_chain"] = {"call": "fd_precond", "n_el": K2_SHAPE["n_el"], "p": K2_SHAPE["p"], "n": n, "R_P": Rp,
                        "ranks": [K2_SHAPE["m"], 1, 1], "GB_per_call": by / 1e9, "ms_per_call": ms / reps,
                        "ms_forward": kk["fd_forward"]["ms"] / reps, "ms_backward": kk["fd_backward"]["ms"] / reps,
-                       "GB_s": gbs, "frac": gbs / PEAK_HBM_GBS}
+                       "GB_s": gbs, "frac": gbs / PEAK_HBM_GBS, "frac_of_copy": gbs / copy_gbs}
+    tf, tb = measured_traffic("fd_forward_batched"), measured_traffic("fd_backward_batched")
+    out["fd_chain"]["traffic_GB_big_launches"] = None if tf is None or tb is None else (tf + tb) / 1e9
     return out
 
 

@@ -55,15 +55,18 @@ struct CopySegs {
 };
 void copy_segments(hipStream_t s, const CopySegs& cs);
 
-// e[j] = sum_i P[i, j]^2 for the a columns of P (rows x a, ld rows)
-void column_energy(hipStream_t s, const double* P, int rows, int a, double* e);
+// Energies e[j] = sum_i P[i, j]^2 of the a columns of P (rows x a, ld rows)
+// as S = column_energy_parts(rows) partial sums per column: part[j * S + s]
+int column_energy_parts(int rows);
+void column_energy(hipStream_t s, const double* P, int rows, int a, double* part);
 
-// Rank choice of one ST-HOSVD mode: sort energies descending, keep the
-// smallest s whose discarded tail is <= budget, where budget =
-// eps^2 * norm2 / 3 and norm2 = *norm2_io (if set_norm, norm2 is first set to
-// sum(e)).  Writes sel[0] = s, sel[1..s] = order; tail energy to disc[0] and
-// s (as a double) to disc[1].
-void select_rank(hipStream_t s, const double* e, int a, double eps, double* norm2_io,
+// Rank choice of one ST-HOSVD mode from the partial energies (e[j] = sum of
+// the S partials of column j): sort energies descending, keep the smallest
+// s whose discarded tail is <= budget, where budget = eps^2 * norm2 / 3 and
+// norm2 = *norm2_io (if set_norm, norm2 is first set to sum(e)).  Writes
+// sel[0] = s, sel[1..s] = order; tail energy to disc[0] and s (as a double)
+// to disc[1].
+void select_rank(hipStream_t s, const double* part, int S, int a, double eps, double* norm2_io,
                  int set_norm, int* sel, double* disc);
 
 // out[:, j] = in[:, idx[j]] for j < s (rows x ., ld rows); idx read from device

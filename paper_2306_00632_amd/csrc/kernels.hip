@@ -455,25 +455,37 @@ void householder_qr(hipStream_t s, const QrJob* jobs, int njobs) {
 // rank selection
 // ---------------------------------------------------------------------------
 
+// Partial energies of the columns of P (rows x a): segment s of column j
+// (kEnergySeg rows) into part[j * S + s]; k_select adds the S partials of a
+// column in a fixed order.
+constexpr int kEnergySeg = 2048;  // 256 threads x 8 rows
+int column_energy_parts(int rows) { return std::max(1, (rows + kEnergySeg - 1) / kEnergySeg); }
+
 __global__ __launch_bounds__(256) void k_column_energy(const double* __restrict__ P, int rows,
-                                                       double* __restrict__ e) {
+                                                       double* __restrict__ part) {
   __shared__ double red[4];
-  const double* col = P + (long long)blockIdx.x * rows;
+  const int j = blockIdx.y, sg = blockIdx.x;
+  const double* col = P + (long long)j * rows;
   double s = 0.0;
-  for (int i = threadIdx.x; i < rows; i += 256) s += col[i] * col[i];
+#pragma unroll
+  for (int u = 0; u < kEnergySeg / 256; ++u) {
+    const int i = sg * kEnergySeg + u * 256 + threadIdx.x;
+    const double v = col[min(i, rows - 1)];  // unconditional load, masked below
+    s += i < rows ? v * v : 0.0;
+  }
   s = block_sum(s, red);
-  if (threadIdx.x == 0) e[blockIdx.x] = s;
+  if (threadIdx.x == 0) part[(long long)j * gridDim.x + sg] = s;
 }
 
-void column_energy(hipStream_t s, const double* P, int rows, int a, double* e) {
-  if (a <= 0) return;
-  hipLaunchKernelGGL(k_column_energy, dim3(a), dim3(256), 0, s, P, rows, e);
+void column_energy(hipStream_t s, const double* P, int rows, int a, double* part) {
+  if (a <= 0 || rows <= 0) return;
+  hipLaunchKernelGGL(k_column_energy, dim3(column_energy_parts(rows), a), dim3(256), 0, s, P, rows, part);
   check_launch("column_energy");
 }
 
 constexpr int kSelMax = 2048;
 
-__global__ __launch_bounds__(1024) void k_select(const double* __restrict__ e, int a, double eps,
+__global__ __launch_bounds__(1024) void k_select(const double* __restrict__ part, int S, int a, double eps,
                                                  double* norm2_io, int set_norm, int* sel,
                                                  double* disc) {
   __shared__ double key[kSelMax];
@@ -481,13 +493,16 @@ __global__ __launch_bounds__(1024) void k_select(const double* __restrict__ e, i
   __shared__ double red[16];
   int P2 = 1;
   while (P2 < a) P2 <<= 1;
-  double part = 0.0;
+  double psum = 0.0;
   for (int i = threadIdx.x; i < P2; i += 1024) {
-    key[i] = (i < a) ? e[i] : -1.0;
+    double ei = 0.0;
+    if (i < a)
+      for (int sg = 0; sg < S; ++sg) ei += part[(long long)i * S + sg];
+    key[i] = (i < a) ? ei : -1.0;
     idx[i] = i;
-    if (i < a) part += e[i];
+    if (i < a) psum += ei;
   }
-  const double tot = block_sum(part, red);
+  const double tot = block_sum(psum, red);
   __syncthreads();
   // bitonic sort, descending by key (ties: ascending index)
   for (int k = 2; k <= P2; k <<= 1) {
@@ -529,10 +544,10 @@ __global__ __launch_bounds__(1024) void k_select(const double* __restrict__ e, i
   for (int i = threadIdx.x; i < s; i += 1024) sel[1 + i] = idx[i];
 }
 
-void select_rank(hipStream_t s, const double* e, int a, double eps, double* norm2_io,
+void select_rank(hipStream_t s, const double* part, int S, int a, double eps, double* norm2_io,
                  int set_norm, int* sel, double* disc) {
   if (a > kSelMax) throw std::runtime_error("select_rank: more than 2048 columns");
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, e, a, eps, norm2_io, set_norm, sel, disc);
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, part, S, a, eps, norm2_io, set_norm, sel, disc);
   check_launch("select_rank");
 }
 
@@ -672,6 +687,17 @@ __device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, int i, bool o
 }
 __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, int i, bool ok, double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tk_u32x2, v), r, ok ? unsigned(i) * 8u : kBufOff, 0, 0);
+}
+
+// Workgroup b of a grid of G is dispatched to XCD b mod 8 (round robin), as
+// the local-th workgroup there (local = b / 8).  xcd_order(b, G) numbers the
+// workgroups XCD by XCD, so consecutive logical indices share an XCD and its
+// L2 (a bijection of [0, G)).
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_order(int b, int G) {
+  const int q = G / kNumXcd, r = G % kNumXcd;
+  const int x = b % kNumXcd, local = b / kNumXcd;
+  return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
 }
 
 constexpr int kFdWave = 64;
@@ -991,10 +1017,11 @@ __global__ __launch_bounds__(kFdWave) void k_fd_backward(FdDev d, const double* 
   constexpr int SL = FdSlot<M>::SIZE;
   __shared__ double2 sm[B * SL];
   const int lane = threadIdx.x, b = lane / P, q = lane % P;
-  // the R_P terms of one column run in consecutive workgroups (the column is
-  // then read from L2 after the first)
+  // the R_P terms of one column run in consecutive logical workgroups on one
+  // XCD (the column is then read from that XCD's L2 after the first)
   const int nj = (d.R + B - 1) / B;
-  const int c = blockIdx.x / nj, jg = blockIdx.x - c * nj;
+  const int lb = xcd_order(blockIdx.x, gridDim.x);
+  const int c = lb / nj, jg = lb - c * nj;
   const int j = jg * B + b;
   const bool valid = j < d.R;
   const double* zc = Zi + (long long)c * d.n;

@@ -404,6 +404,9 @@ struct TruncPrep {
   BufP Q[3];        // n_k x q_k (unless ident)
   BufP Z;           // q0 x q1 x q2
   double norm2 = 0; // ||Z||^2 (set by the first ST-HOSVD mode)
+  // the first ST-HOSVD mode depends on Z only: its eigenvectors, projection
+  // and energies are kept for the retries of Algorithm 2 on the same tensor
+  BufP V0, Pm0, part0;
 };
 
 static TruncPrep truncate_prepare(tk_ctx* ctx, const tk_tucker* y) {
@@ -499,24 +502,41 @@ static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double*
   bool zero = (zsz == 0);
   for (int k = 0; k < 3 && !zero; ++k) {
     const int a = dims[0], bc = dims[1] * dims[2];
-    // Gram of the mode-k unfolding (the current leading mode)
-    BufP G = alloc(ctx, (size_t)a * a);
-    gemm(ctx, false, true, a, a, bc, 1.0, cur->p, a, cur->p, a, 0.0, G->p, a);
-    BufP V = alloc(ctx, (size_t)a * a), w = alloc(ctx, (size_t)a);
-    {
-      BufP work = alloc(ctx, gpu::sym_eig_work(a));
-      Prof pr(ctx, PK_EIG, 8.0 * 2.0 * a * (double)a, eig_flops(a));
-      gpu::sym_eig(ctx->stream, G->p, a, V->p, w->p, work->p);
+    const int nseg = gpu::column_energy_parts(bc);
+    BufP V, Pm, part;
+    if (k == 0 && P.V0) {
+      V = P.V0;
+      Pm = P.Pm0;
+      part = P.part0;
+    } else {
+      // Gram of the mode-k unfolding (the current leading mode)
+      BufP G = alloc(ctx, (size_t)a * a);
+      gemm(ctx, false, true, a, a, bc, 1.0, cur->p, a, cur->p, a, 0.0, G->p, a);
+      V = alloc(ctx, (size_t)a * a);
+      BufP w = alloc(ctx, (size_t)a);
+      {
+        BufP work = alloc(ctx, gpu::sym_eig_work(a));
+        Prof pr(ctx, PK_EIG, 8.0 * 2.0 * a * (double)a, eig_flops(a));
+        gpu::sym_eig(ctx->stream, G->p, a, V->p, w->p, work->p);
+      }
+      // P = A^T V (bc x a): columns are the mode-k coordinates in the eigenbasis
+      Pm = alloc(ctx, (size_t)bc * a);
+      gemm(ctx, true, false, bc, a, a, 1.0, cur->p, a, V->p, a, 0.0, Pm->p, bc);
+      part = alloc(ctx, (size_t)a * nseg);
+      {
+        Prof pr(ctx, PK_SELECT, 8.0 * bc * (double)a, 2.0 * bc * (double)a);
+        gpu::column_energy(ctx->stream, Pm->p, bc, a, part->p);
+      }
+      if (k == 0) {
+        P.V0 = V;
+        P.Pm0 = Pm;
+        P.part0 = part;
+      }
     }
-    // P = A^T V (bc x a): columns are the mode-k coordinates in the eigenbasis
-    BufP Pm = alloc(ctx, (size_t)bc * a);
-    gemm(ctx, true, false, bc, a, a, 1.0, cur->p, a, V->p, a, 0.0, Pm->p, bc);
-    BufP e = alloc(ctx, (size_t)a);
     int* sel = reinterpret_cast<int*>(ctx->sel->p);
     {
-      Prof pr(ctx, PK_SELECT, 8.0 * bc * (double)a, 2.0 * bc * (double)a);
-      gpu::column_energy(ctx->stream, Pm->p, bc, a, e->p);
-      gpu::select_rank(ctx->stream, e->p, a, eps, norm2, k == 0 ? 1 : 0, sel, disc);
+      Prof pr(ctx, PK_SELECT, 8.0 * a * (double)nseg, 0.0);
+      gpu::select_rank(ctx->stream, part->p, nseg, a, eps, norm2, k == 0 ? 1 : 0, sel, disc);
     }
     // one readback of [norm2, tail, s] (scal + 300 .. 302)
     const auto hv = d2h(ctx, norm2, 3);
