@@ -42,10 +42,10 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 # source file holding the kernels of each instrumented family
-FAMILY_SOURCE = {"sym_eig": "eig.hip", "dgemm": "kernels.hip", "band_apply": "kernels.hip",
-                 "select_rank": "kernels.hip", "fd_forward": "kernels.hip", "fd_backward": "kernels.hip",
-                 "householder_qr": "kernels.hip", "band_apply_batched": "kernels.hip",
-                 "fd_forward_batched": "kernels.hip", "fd_backward_batched": "kernels.hip"}
+FAMILY_SOURCE = {"sym_eig": "eig.hip", "dgemm": "gemm.hip", "band_apply": "modeprod.hip",
+                 "select_rank": "kernels.hip", "fd_forward": "modeprod.hip", "fd_backward": "modeprod.hip",
+                 "householder_qr": "kernels.hip", "band_apply_batched": "modeprod.hip",
+                 "fd_forward_batched": "modeprod.hip", "fd_backward_batched": "modeprod.hip"}
 
 
 def measured_traffic(family):

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtk.so")
-SOURCES = ["kernels.hip", "eig.hip", "runtime.cpp", "setup_bspline.cpp", "setup_fd.cpp", "setup_expsum.cpp"]
+SOURCES = ["kernels.hip", "modeprod.hip", "gemm.hip", "eig.hip", "runtime.cpp", "setup_bspline.cpp", "setup_fd.cpp", "setup_expsum.cpp"]
 
 
 def hipcc() -> str:

@@ -1,23 +1,15 @@
-// HIP kernels for gfx950 (CDNA4, wave64) of the Tucker TPCG library.
+// HIP kernels for gfx950 (CDNA4, wave64) of the Tucker TPCG library: the
+// pieces of the truncation (Algorithm 1) and the vector arithmetic.
 //
-//  band_apply     banded mode products A_(k,t) X_k of eq. (tt_product): one
-//                 workgroup stages 256-row windows of 8 factor columns in LDS
-//                 and applies every 1D matrix of the mode to them, a row's
-//                 band entries held in registers (coalesced along n, the
-//                 factor is read from HBM once).
 //  householder_qr QR of stacked factors (Algorithm 1, step 1), one workgroup
 //                 per mode, one wavefront per trailing column.
-//  dgemm          FP64 MFMA GEMM (v_mfma_f64_16x16x4f64 tiles, LDS double
-//                 buffering, deterministic split-K).
 //  column_energy, select_rank, gather_columns
 //                 the rank choice of each ST-HOSVD mode from directly
 //                 measured energies ||A^T v_j||^2.
-//  fd_forward / fd_backward
-//                 the low-rank FD transform U~^T and U~ D_j (Algorithm 4,
-//                 Appendix B): sparse boundary maps around sine transforms
-//                 of length N, each one complex FFT of length N/2 held in the
-//                 registers of one wavefront (DST-I for odd p, DST-II/III
-//                 for even p).
+//  dot_accumulate, copy_segments, fill, scale_copy
+//                 reductions and copies of Tucker data.
+// The mode products are in modeprod.hip, the FP64 GEMM in gemm.hip and the
+// symmetric eigensolver in eig.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,350 +17,11 @@
 #include <stdexcept>
 #include <string>
 
+#include "device_common.h"
 #include "kernels.h"
 
 namespace tk {
 namespace gpu {
-
-static void check_launch(const char* what) {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
-}
-
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// block-wide sum; `red` is LDS of >= blockDim.x/64 doubles; result to all threads
-__device__ double block_sum(double v, double* red) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int nw = (blockDim.x + 63) >> 6;
-  v = wave_sum(v);
-  __syncthreads();
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int i = 0; i < nw; ++i) t += red[i];
-  return t;
-}
-
-// ---------------------------------------------------------------------------
-// banded mode products
-// ---------------------------------------------------------------------------
-
-constexpr int kBandRows = 256;   // rows of a factor column per workgroup
-constexpr int kBandCols = 8;     // factor columns per workgroup (band rows reused across them)
-
-// W[:, t*m + c] = A_t Y[:, c]: a workgroup stages kBandCols windows of 256 + 2p
-// rows of Y in LDS; each thread keeps the 2p + 1 band entries of its row of
-// A_t in registers, loading those of A_{t+1} while it applies A_t to every
-// staged column.  All loads are unconditional (clamped indices), only
-// stores are guarded, so the loads of a step issue together.
-template <int PD>
-__global__ __launch_bounds__(kBandRows) void k_band_apply(int n, int m, int nmat, const double* __restrict__ band,
-                                                          const double* __restrict__ Y, int ldy,
-                                                          double* __restrict__ W, int ldw) {
-  constexpr int NB = 2 * PD + 1, WIN = kBandRows + 2 * PD;
-  __shared__ double ys[kBandCols * WIN];
-  const int i0 = blockIdx.x * kBandRows;
-  const int c0 = blockIdx.y * kBandCols;
-  const int nc = min(kBandCols, m - c0);
-#pragma unroll
-  for (int cc = 0; cc < kBandCols; ++cc) {
-    const double* col = Y + (long long)(c0 + min(cc, nc - 1)) * ldy;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int t = min((int)threadIdx.x + h * kBandRows, WIN - 1);
-      const int i = i0 - PD + t;
-      const double v = col[min(max(i, 0), n - 1)];
-      ys[cc * WIN + t] = (i >= 0 && i < n) ? v : 0.0;
-    }
-  }
-  __syncthreads();
-  const int i = i0 + threadIdx.x;
-  if (i >= n) return;
-  double bv[NB], bnext[NB];
-#pragma unroll
-  for (int o = 0; o < NB; ++o) bv[o] = band[(long long)o * n + i];
-  for (int t = 0; t < nmat; ++t) {
-    const double* bt = band + (long long)min(t + 1, nmat - 1) * NB * n + i;
-#pragma unroll
-    for (int o = 0; o < NB; ++o) bnext[o] = bt[(long long)o * n];
-#pragma unroll
-    for (int cc = 0; cc < kBandCols; ++cc) {
-      const double* yw = ys + cc * WIN + threadIdx.x;
-      double acc = 0.0;
-#pragma unroll
-      for (int o = 0; o < NB; ++o) acc += bv[o] * yw[o];
-      if (cc < nc) W[i + (long long)(t * m + c0 + cc) * ldw] = acc;
-    }
-#pragma unroll
-    for (int o = 0; o < NB; ++o) bv[o] = bnext[o];
-  }
-}
-
-void band_apply(hipStream_t s, int n, int m, int nmat, int p, const double* band,
-                const double* Y, int ldy, double* W, int ldw) {
-  if (n <= 0 || m <= 0 || nmat <= 0) return;
-  dim3 grid((n + kBandRows - 1) / kBandRows, (m + kBandCols - 1) / kBandCols);
-  if (grid.y > 65535) throw std::runtime_error("band_apply: more than 524280 columns");
-  switch (p) {
-#define TK_BAND(PD) \
-  case PD: hipLaunchKernelGGL(k_band_apply<PD>, grid, dim3(kBandRows), 0, s, n, m, nmat, band, Y, ldy, W, ldw); break;
-    TK_BAND(0) TK_BAND(1) TK_BAND(2) TK_BAND(3) TK_BAND(4) TK_BAND(5) TK_BAND(6)
-#undef TK_BAND
-    default: throw std::runtime_error("band_apply: half-bandwidth above 6");
-  }
-  check_launch("band_apply");
-}
-
-// ---------------------------------------------------------------------------
-// FP64 GEMM
-// ---------------------------------------------------------------------------
-
-// FP64 GEMM on the matrix cores (v_mfma_f64_16x16x4f64).  A workgroup of WM
-// wavefronts computes a (16 WM) x (16 NT) tile of C; wavefront w owns rows
-// [16w, 16w+16) and NT column tiles of 16, i.e. NT 16x16 accumulators.  K is
-// staged through LDS in steps of BK = 16 (double buffered: the next step's
-// global loads are in flight while the current step is multiplied).  The
-// tile leaves through LDS, 48 columns at a time, so every column of C is
-// written (and, with beta != 0, read) as one contiguous run of rows.
-// Operand layout of the instruction (lane l, element v): A[l%16][l/16],
-// B[l/16][l%16], D[l/16 + 4v][l%16].
-constexpr int BK = 16;
-
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-template <int WM, int NT>
-struct GemmLds {
-  static constexpr int BM = 16 * WM, BN = 16 * NT;
-  static constexpr int kAPad = BM + 1, kBPad = BN + 1;  // odd strides: conflict-free transposing stores
-  static constexpr int kOps = 2 * BK * (kAPad + kBPad);  // double-buffered A and B tiles
-  static constexpr int kOut = 48 * kAPad;                // 48 output columns staged at a time
-  static constexpr int kSize = kOps > kOut ? kOps : kOut;
-};
-
-// With `part` set, blockIdx.z selects the K range [z*kchunk, (z+1)*kchunk)
-// and alpha*op(A)op(B) over that range is written to part + z*M*N (ld M);
-// otherwise blockIdx.z is the batch index.
-template <bool TA, bool TB, int WM, int NT>
-__global__ __launch_bounds__(64 * WM) void k_dgemm(int M, int N, int K, double alpha,
-                                                   const double* __restrict__ A, int lda, long long sA,
-                                                   const double* __restrict__ B, int ldb, long long sB,
-                                                   double beta, double* __restrict__ C, int ldc,
-                                                   long long sC, int kchunk, double* __restrict__ part) {
-  using Lds = GemmLds<WM, NT>;
-  constexpr int NTH = 64 * WM;
-  constexpr int BM = Lds::BM, BN = Lds::BN, kAPad = Lds::kAPad, kBPad = Lds::kBPad;
-  constexpr int kALoads = BM * BK / NTH;  // 4
-  constexpr int kBLoads = (BN * BK + NTH - 1) / NTH;
-  constexpr bool kBTail = BN * BK % NTH != 0;  // last B load round only partly used
-  static_assert(BM * BK % NTH == 0, "A tile loads must divide evenly");
-  __shared__ double smem[Lds::kSize];
-  double(*As)[BK][kAPad] = reinterpret_cast<double(*)[BK][kAPad]>(smem);
-  double(*Bs)[BK][kBPad] = reinterpret_cast<double(*)[BK][kBPad]>(smem + 2 * BK * kAPad);
-  int kbeg = 0, kend = K;
-  if (part) {
-    kbeg = blockIdx.z * kchunk;
-    kend = min(K, kbeg + kchunk);
-    C = part + (long long)blockIdx.z * M * N;
-    ldc = M;
-    beta = 0.0;
-  } else {
-    A += sA * blockIdx.z;
-    B += sB * blockIdx.z;
-    C += sC * blockIdx.z;
-  }
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int row0 = blockIdx.x * BM, col0 = blockIdx.y * BN;
-  double ra[kALoads], rb[kBLoads];
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int l = 0; l < kALoads; ++l) {
-      const int e = t + NTH * l;
-      const int i = TA ? e / BK : e % BM, kk = TA ? e % BK : e / BM;
-      const int gr = row0 + i, gk = k0 + kk;
-      ra[l] = (gr < M && gk < kend) ? (TA ? A[gk + (long long)gr * lda] : A[gr + (long long)gk * lda]) : 0.0;
-    }
-#pragma unroll
-    for (int l = 0; l < kBLoads; ++l) {
-      const int e = t + NTH * l;
-      const int j = TB ? e % BN : e / BK, kk = TB ? e / BN : e % BK;
-      const int gc = col0 + j, gk = k0 + kk;
-      const bool in = !kBTail || e < BN * BK;
-      rb[l] = (in && gc < N && gk < kend) ? (TB ? B[gc + (long long)gk * ldb] : B[gk + (long long)gc * ldb]) : 0.0;
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int l = 0; l < kALoads; ++l) {
-      const int e = t + NTH * l;
-      const int i = TA ? e / BK : e % BM, kk = TA ? e % BK : e / BM;
-      As[buf][kk][i] = ra[l];
-    }
-#pragma unroll
-    for (int l = 0; l < kBLoads; ++l) {
-      const int e = t + NTH * l;
-      const int j = TB ? e % BN : e / BK, kk = TB ? e / BN : e % BK;
-      if (!kBTail || e < BN * BK) Bs[buf][kk][j] = rb[l];
-    }
-  };
-  dbl4 acc[NT];
-#pragma unroll
-  for (int j = 0; j < NT; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  const int fr = 16 * wv + (lane & 15);  // A fragment row within the tile
-  const int fk = lane >> 4;              // fragment k within a step of 4
-  const int fc = lane & 15;              // B fragment column within a 16-wide tile
-  int buf = 0;
-  if (kbeg < kend) {
-    load(kbeg);
-    store(0);
-  }
-  __syncthreads();
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    const bool more = k0 + BK < kend;
-    if (more) load(k0 + BK);
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 4) {
-      const double af = As[buf][ks + fk][fr];
-#pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        const double bf = Bs[buf][ks + fk][16 * j + fc];
-        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc[j], 0, 0, 0);
-      }
-    }
-    if (more) store(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
-  }
-  // epilogue through LDS (the operand tiles are free after the last barrier)
-  double(*Cs)[kAPad] = reinterpret_cast<double(*)[kAPad]>(smem);
-#pragma unroll
-  for (int j0 = 0; j0 < NT; j0 += 3) {
-#pragma unroll
-    for (int j = j0; j < j0 + 3 && j < NT; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Cs[16 * (j - j0) + fc][16 * wv + (lane >> 4) + 4 * v] = acc[j][v];
-    __syncthreads();
-    const int ncol = min(48, BN - 16 * j0);
-    for (int e = t; e < ncol * BM; e += NTH) {
-      const int i = e % BM, jc = e / BM;
-      const int gr = row0 + i, gc = col0 + 16 * j0 + jc;
-      if (gr < M && gc < N) {
-        double* cp = C + gr + (long long)gc * ldc;
-        const double val = alpha * Cs[jc][i];
-        *cp = (beta == 0.0) ? val : val + beta * (*cp);
-      }
-    }
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(256) void k_splitk_reduce(int M, int N, int nsplit, const double* __restrict__ part,
-                                                       double beta, double* __restrict__ C, int ldc) {
-  const long long MN = (long long)M * N;
-  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < MN; e += 256LL * gridDim.x) {
-    // partial sums added in split order; the loads of eight splits are issued together
-    double acc = 0.0;
-    int z = 0;
-    for (; z + 8 <= nsplit; z += 8) {
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = part[(z + u) * MN + e];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc += v[u];
-    }
-    for (; z < nsplit; ++z) acc += part[z * MN + e];
-    const int i = int(e % M), j = int(e / M);
-    double* cp = C + i + (long long)j * ldc;
-    *cp = (beta == 0.0) ? acc : acc + beta * (*cp);
-  }
-}
-
-// row tiles of 16 per workgroup: 3 for short products where 48-row tiles pad
-// M less than 64-row tiles, 4 otherwise
-static int dgemm_wm(int M) {
-  const long long p64 = (M + 63) / 64 * 64LL, p48 = (M + 47) / 48 * 48LL;
-  return (M <= 144 && p48 < p64) ? 3 : 4;
-}
-// column tiles of 16 per workgroup for an N-wide product; 48-column tiles
-// (same padding for N in (96, 144]) when the wide tile would leave fewer than
-// two workgroups per compute unit to hide the global-load latency
-static int dgemm_nt(int M, int N, int batch) {
-  const int nt = N <= 32 ? 2 : N <= 64 ? 4 : N <= 96 ? 6 : 9;
-  if (nt == 9) {
-    const int bm = 16 * dgemm_wm(M);
-    const long long blocks = (long long)((M + bm - 1) / bm) * ((N + 143) / 144) * batch;
-    const long long p144 = (N + 143) / 144 * 144LL, p48 = (N + 47) / 48 * 48LL;
-    if (blocks < 512 && p48 <= p144) return 3;
-  }
-  return nt;
-}
-
-int dgemm_split_count(int M, int N, int K) {
-  const int bn = 16 * dgemm_nt(M, N, 1), bm = 16 * dgemm_wm(M);
-  const long long tiles = (long long)((M + bm - 1) / bm) * ((N + bn - 1) / bn);
-  if (tiles >= 128 || K < 1024) return 1;
-  long long ns = std::min<long long>(K / 256, 256 / std::max<long long>(tiles, 1));
-  return (int)std::max<long long>(1, std::min<long long>(ns, 64));
-}
-
-template <int WM, int NT>
-static void launch_dgemm(hipStream_t s, bool ta, bool tb, dim3 grid, int M, int N, int K, double alpha,
-                         const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
-                         double beta, double* C, int ldc, long long sC, int kchunk, double* part) {
-  const dim3 blk(64 * WM);
-  if (!ta && !tb) hipLaunchKernelGGL((k_dgemm<false, false, WM, NT>), grid, blk, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
-  else if (ta && !tb) hipLaunchKernelGGL((k_dgemm<true, false, WM, NT>), grid, blk, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
-  else if (!ta && tb) hipLaunchKernelGGL((k_dgemm<false, true, WM, NT>), grid, blk, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
-  else hipLaunchKernelGGL((k_dgemm<true, true, WM, NT>), grid, blk, 0, s, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
-}
-
-template <int WM>
-static void launch_dgemm_nt(hipStream_t s, int nt, bool ta, bool tb, dim3 grid, int M, int N, int K, double alpha,
-                            const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
-                            double beta, double* C, int ldc, long long sC, int kchunk, double* part) {
-  switch (nt) {
-    case 2: launch_dgemm<WM, 2>(s, ta, tb, grid, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part); break;
-    case 3: launch_dgemm<WM, 3>(s, ta, tb, grid, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part); break;
-    case 4: launch_dgemm<WM, 4>(s, ta, tb, grid, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part); break;
-    case 6: launch_dgemm<WM, 6>(s, ta, tb, grid, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part); break;
-    default: launch_dgemm<WM, 9>(s, ta, tb, grid, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part); break;
-  }
-}
-
-void dgemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
-           const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
-           double beta, double* C, int ldc, long long sC, int batch, double* part, int nsplit) {
-  if (M <= 0 || N <= 0 || batch <= 0) return;
-  if (K <= 0) {
-    if (beta == 1.0) return;
-    // C = beta C
-    for (int b = 0; b < batch; ++b)
-      for (int j = 0; j < N; ++j) scale_copy(s, C + sC * b + (long long)j * ldc, M, beta, C + sC * b + (long long)j * ldc);
-    return;
-  }
-  int kchunk = K;
-  int gz = batch;
-  if (part && nsplit > 1 && batch == 1) {
-    kchunk = ((K + nsplit - 1) / nsplit + BK - 1) / BK * BK;
-    gz = (K + kchunk - 1) / kchunk;
-  } else {
-    part = nullptr;
-  }
-  const int nt = dgemm_nt(M, N, gz), wm = dgemm_wm(M);
-  dim3 grid((M + 16 * wm - 1) / (16 * wm), (N + 16 * nt - 1) / (16 * nt), gz);
-  if (wm == 3) launch_dgemm_nt<3>(s, nt, ta, tb, grid, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
-  else launch_dgemm_nt<4>(s, nt, ta, tb, grid, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, kchunk, part);
-  check_launch("dgemm");
-  if (part) {
-    const long long MN = (long long)M * N;
-    const int nb = (int)std::min<long long>(1024, (MN + 255) / 256);
-    hipLaunchKernelGGL(k_splitk_reduce, dim3(nb), dim3(256), 0, s, M, N, gz, part, beta, C, ldc);
-    check_launch("splitk_reduce");
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Householder QR
@@ -642,552 +295,6 @@ void scale_copy(hipStream_t s, const double* x, long long n, double a, double* y
   const int nb = (int)std::min<long long>(1024, (n + 255) / 256);
   hipLaunchKernelGGL(k_scale_copy, dim3(nb), dim3(256), 0, s, x, n, a, y);
   check_launch("scale_copy");
-}
-
-// ---------------------------------------------------------------------------
-// low-rank FD transform (Algorithm 4): sine transforms of length N = n_el
-// through one complex FFT of length M = N/2 per transform
-// ---------------------------------------------------------------------------
-//
-// A workgroup is one wavefront.  Every lane holds RL = min(8, M) complex
-// values of a transform, P = M / RL lanes share one transform and a wave
-// runs B = 64 / P transforms side by side (slot b = lane / P), each in its
-// own M-element LDS region.  The FFT is a Stockham sequence of radix-8 passes
-// (a final radix-4 or radix-2 pass when log2 M is not a multiple of 3), the
-// butterflies in registers and one LDS exchange per pass.
-//
-// Real transforms on top of it (x_0 = x_N = 0 where it applies):
-//  * DST-I   F_k = sum_{j=1}^{N-1} x_j sin(pi j k / N): the real DFT of
-//    y_j = sin(pi j/N)(x_j + x_{N-j}) + (x_j - x_{N-j})/2 gives F_{2k} = -Im Y_k
-//    and F_{2k+1} - F_{2k-1} = Re Y_k (F_1 = Re Y_0 / 2), a prefix sum;
-//  * DST-II  S_k = sum_{m<N} x_m sin(pi (2m+1) k / 2N): the DCT-II of
-//    (-1)^m x_m read backwards, through the even/odd reordering of the
-//    input and one real DFT of length N;
-//  * DST-III T_m = sum_{k=1}^{N} w_{k-1} sin(pi k (2m+1) / 2N): DST-II
-//    applied in reverse (its rows are orthogonal with squared norms N/2,
-//    and N for the last one).
-// A real DFT of length N is one complex FFT of length M of the even/odd
-// samples packed as (re, im) plus an O(N) split.
-
-// Raw buffer access: a resource covers `count` doubles from a base that is
-// the same for the whole wave (so it lives in scalar registers); a lane that
-// must not touch memory passes an offset past the range instead.  The
-// hardware range check returns 0 for such loads and drops such stores, so
-// the ragged ends of unrolled loops need no branches (a branch around a load
-// lets the compiler sink the load next to its use and serialise the waits).
-typedef unsigned int tk_u32x2 __attribute__((ext_vector_type(2)));
-constexpr int kBufWord3 = 0x00020000;      // 32-bit data format, gfx9 family
-constexpr unsigned kBufOff = 0xFFFFFFF8u;  // an offset past every range
-constexpr unsigned long long kBufOffHost = 0xFFFFFFF0ull;
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const double* p, long long count) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0, (int)(unsigned)(count * 8), kBufWord3);
-}
-__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, int i, bool ok) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, ok ? unsigned(i) * 8u : kBufOff, 0, 0));
-}
-__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, int i, bool ok, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(tk_u32x2, v), r, ok ? unsigned(i) * 8u : kBufOff, 0, 0);
-}
-
-// Workgroup b of a grid of G is dispatched to XCD b mod 8 (round robin), as
-// the local-th workgroup there (local = b / 8).  xcd_order(b, G) numbers the
-// workgroups XCD by XCD, so consecutive logical indices share an XCD and its
-// L2 (a bijection of [0, G)).
-constexpr int kNumXcd = 8;
-__device__ __forceinline__ int xcd_order(int b, int G) {
-  const int q = G / kNumXcd, r = G % kNumXcd;
-  const int x = b % kNumXcd, local = b / kNumXcd;
-  return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
-}
-
-constexpr int kFdWave = 64;
-constexpr int kFdMaxV2 = 4;  // V_2 columns: p - 1 or p - 2, at most 4 for p <= 6
-
-template <int M>
-struct FdShape {
-  static constexpr int RL = M < 8 ? M : 8;
-  static constexpr int P = M / RL;
-  static constexpr int B = kFdWave / P;
-};
-
-// LDS views of a slot, padded against bank conflicts (lanes that touch 8
-// consecutive complex or 16 consecutive real elements each): complex element
-// i sits at i + i/8, real element i at i + i/16; the two views alias.
-template <int M>
-struct FdSlot {
-  static constexpr int SIZE = M + M / 8;  // complex elements
-};
-struct CBuf {
-  double2* p;
-  __device__ __forceinline__ double2& operator[](int i) const { return p[i + (i >> 3)]; }
-};
-struct RBuf {
-  double* p;
-  __device__ __forceinline__ double& operator[](int i) const { return p[i + (i >> 4)]; }
-};
-
-__device__ __forceinline__ double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 c_mul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 c_conj(double2 a) { return make_double2(a.x, -a.y); }
-// multiply by SIGN * i
-template <int SIGN>
-__device__ __forceinline__ double2 c_rot(double2 a) {
-  return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
-}
-
-// in-register DFT of length R with kernel exp(SIGN 2 pi i t k / R)
-template <int R, int SIGN>
-__device__ __forceinline__ void dft_reg(double2* v) {
-  if constexpr (R == 2) {
-    const double2 t = v[1];
-    v[1] = c_sub(v[0], t);
-    v[0] = c_add(v[0], t);
-  } else if constexpr (R == 4) {
-    const double2 t0 = c_add(v[0], v[2]), t1 = c_sub(v[0], v[2]);
-    const double2 t2 = c_add(v[1], v[3]), t3 = c_rot<SIGN>(c_sub(v[1], v[3]));
-    v[0] = c_add(t0, t2);
-    v[2] = c_sub(t0, t2);
-    v[1] = c_add(t1, t3);
-    v[3] = c_sub(t1, t3);
-  } else {
-    static_assert(R == 8, "radix");
-    double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
-    dft_reg<4, SIGN>(e);
-    dft_reg<4, SIGN>(o);
-    constexpr double h = 0.70710678118654752440;
-    // o_k *= exp(SIGN 2 pi i k / 8)
-    o[1] = make_double2(h * (o[1].x - SIGN * o[1].y), h * (o[1].y + SIGN * o[1].x));
-    o[2] = c_rot<SIGN>(o[2]);
-    o[3] = make_double2(h * (-o[3].x - SIGN * o[3].y), h * (-o[3].y + SIGN * o[3].x));
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      v[k] = c_add(e[k], o[k]);
-      v[k + 4] = c_sub(e[k], o[k]);
-    }
-  }
-}
-
-// Stockham passes from stride NS on.  On entry to the first pass (NS = 1)
-// a[t] holds element q + t P of the lane's transform; every pass leaves its
-// result in `buf` (M elements, natural order after the last pass).
-template <int M, int SIGN, int NS>
-__device__ __forceinline__ void fft_passes(double2* a, CBuf buf, int q, const double2* __restrict__ cs) {
-  if constexpr (NS < M) {
-    constexpr int RL = FdShape<M>::RL, P = FdShape<M>::P;
-    constexpr int R = (M / NS) >= 8 ? 8 : (M / NS);
-    constexpr int NB = RL / R;  // butterflies per lane
-    if constexpr (NS > 1) {
-#pragma unroll
-      for (int u = 0; u < NB; ++u)
-#pragma unroll
-        for (int t = 0; t < R; ++t) a[u * R + t] = buf[q + P * u + t * (M / R)];
-    }
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int j = q + P * u;
-      const int k = j & (NS - 1);
-      if constexpr (NS > 1) {
-#pragma unroll
-        for (int t = 1; t < R; ++t) {
-          double2 w = cs[2 * t * k * (M / (NS * R))];
-          if (SIGN > 0) w.y = -w.y;
-          a[u * R + t] = c_mul(a[u * R + t], w);
-        }
-      }
-      dft_reg<R, SIGN>(a + u * R);
-    }
-    if constexpr (NS > 1) __syncthreads();  // every lane has read this pass's input
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int j = q + P * u;
-      const int k = j & (NS - 1);
-#pragma unroll
-      for (int t = 0; t < R; ++t) buf[(j - k) * R + k + t * NS] = a[u * R + t];
-    }
-    __syncthreads();
-    fft_passes<M, SIGN, NS * R>(a, buf, q, cs);
-  }
-}
-
-// segmented inclusive prefix sum over the P lanes of a slot
-template <int P>
-__device__ __forceinline__ double seg_scan(double v, int q) {
-#pragma unroll
-  for (int d = 1; d < P; d <<= 1) {
-    const double o = __shfl_up(v, d, P);
-    if (q >= d) v += o;
-  }
-  return v;
-}
-
-template <int P>
-__device__ __forceinline__ double seg_sum(double v) {
-#pragma unroll
-  for (int d = P >> 1; d > 0; d >>= 1) v += __shfl_xor(v, d, P);
-  return v;
-}
-
-// DST-I pre-processing: a[t] = (y_{2e}, y_{2e+1}) for e = q + t P, x(j) for
-// 0 <= j <= N (zero at both ends)
-template <int M, class X>
-__device__ __forceinline__ void dst1_pre(double2* a, int q, const double* __restrict__ sn, X x) {
-  constexpr int N = 2 * M, RL = FdShape<M>::RL, P = FdShape<M>::P;
-#pragma unroll
-  for (int t = 0; t < RL; ++t) {
-    const int e = q + t * P;
-    double y[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int j = 2 * e + h;
-      const double xa = x(j), xb = x(N - j);
-      y[h] = sn[j] * (xa + xb) + 0.5 * (xa - xb);
-    }
-    a[t] = make_double2(y[0], y[1]);
-  }
-}
-
-// The real DFT bin k (0 <= k <= M) of the packed FFT Z: E + exp(-2 pi i k/N) O.
-template <int M>
-__device__ __forceinline__ double2 real_bin(CBuf Z, int k, const double2* __restrict__ cs) {
-  const double2 zk = Z[k & (M - 1)], zc = c_conj(Z[(M - k) & (M - 1)]);
-  const double2 e = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
-  const double2 d = c_sub(zk, zc);
-  const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);  // -i/2 (zk - zc)
-  double2 w = k < M ? cs[k] : make_double2(-1.0, 0.0);
-  return c_add(e, c_mul(w, o));
-}
-
-// DST-I post-processing: F_f (f = 1..N-1) into cv[f - 1] (cv aliases Z)
-template <int M>
-__device__ __forceinline__ void dst1_post(CBuf Z, RBuf cv, int q, const double2* __restrict__ cs) {
-  constexpr int RL = FdShape<M>::RL, P = FdShape<M>::P;
-  double R[RL], I[RL];
-#pragma unroll
-  for (int s = 0; s < RL; ++s) {
-    const int k = q * RL + s;
-    const double2 y = real_bin<M>(Z, k, cs);
-    R[s] = (k == 0) ? 0.5 * y.x : y.x;
-    I[s] = -y.y;
-  }
-#pragma unroll
-  for (int s = 1; s < RL; ++s) R[s] += R[s - 1];
-  const double tot = seg_scan<P>(R[RL - 1], q);
-  const double base = tot - R[RL - 1];
-  __syncthreads();  // every lane has read Z
-#pragma unroll
-  for (int s = 0; s < RL; ++s) {
-    const int k = q * RL + s;
-    cv[2 * k] = base + R[s];
-    if (k > 0) cv[2 * k - 1] = I[s];
-  }
-  __syncthreads();
-}
-
-// DST-II post-processing: S_s (s = 1..N) into cv[s - 1]
-template <int M>
-__device__ __forceinline__ void dst2_post(CBuf Z, RBuf cv, int q, const double2* __restrict__ cs,
-                                          const double2* __restrict__ tq) {
-  constexpr int N = 2 * M, RL = FdShape<M>::RL;
-  double re[RL], im[RL];
-  double sm = 0.0;
-#pragma unroll
-  for (int s = 0; s < RL; ++s) {
-    const int k = q * RL + s;
-    const double2 v = c_mul(tq[k], real_bin<M>(Z, k, cs));
-    re[s] = v.x;
-    im[s] = -v.y;
-  }
-  if (q == 0) {
-    const double2 z0 = Z[0];
-    sm = (tq[M].x * (z0.x - z0.y));  // Re(tq_M (Re Z_0 - Im Z_0))
-  }
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < RL; ++s) {
-    const int k = q * RL + s;
-    cv[N - k - 1] = re[s];
-    if (k > 0) cv[k - 1] = im[s];
-  }
-  if (q == 0) cv[M - 1] = sm;
-  __syncthreads();
-}
-
-// Z = U~^T S column by column (Algorithm 4, step 5): t = E^T s staged in
-// LDS, the sine transform, times g; the V_2 coefficients are plain dot
-// products.
-template <int M, bool ODD>
-__global__ __launch_bounds__(kFdWave) void k_fd_forward(FdDev d, const double* __restrict__ S, int lds_, int r,
-                                                        double* __restrict__ Zo) {
-  constexpr int N = 2 * M, RL = FdShape<M>::RL, P = FdShape<M>::P, B = FdShape<M>::B;
-  constexpr int SL = FdSlot<M>::SIZE;
-  __shared__ double2 sm[B * SL];
-  const int lane = threadIdx.x, b = lane / P, q = lane % P;
-  const int c = blockIdx.x * B + b;
-  const bool valid = c < r;
-  const double* s = S + (long long)(valid ? c : r - 1) * lds_;
-  const CBuf Z{sm + b * SL};
-  const RBuf cv{reinterpret_cast<double*>(sm + b * SL)};
-  // interior rows of E^T (a shifted copy): at most N = 2 RL P, 2 RL per lane;
-  // the loads are clamped into range so that they issue together
-  // the B input columns of the workgroup through one resource
-  const int c0 = blockIdx.x * B;
-  const auto rs = buf_rsrc(S + (long long)c0 * lds_, (long long)(B - 1) * lds_ + d.n);
-  const int sb = b * lds_;
-  // rows m < N, 2 RL per lane: the interior ones copy s[m + et_sh]
-#pragma unroll
-  for (int u = 0; u < 2 * RL; ++u) {
-    const int m = q + P * u;
-    const bool in = valid && m >= d.et_lo && m < d.et_hi;
-    cv[m] = buf_ld(rs, sb + m + d.et_sh, in);
-  }
-  // boundary rows [0, et_lo) and [et_hi, n1) through the ELL table, each by
-  // the lane that wrote it above
-  for (int m = q; m < d.n1; m += P) {
-    if (m >= d.et_lo && m < d.et_hi) continue;
-    double t = 0.0;
-    for (int k = 0; k < d.ket; ++k) {
-      const int src = d.et_idx[m * d.ket + k];
-      if (src >= 0) t += d.et_val[m * d.ket + k] * s[src];
-    }
-    cv[m] = t;
-  }
-  __syncthreads();
-  double2 a[RL];
-  if constexpr (ODD) {
-    dst1_pre<M>(a, q, d.sn, [&](int j) {
-      const double x = cv[min(max(j - 1, 0), N - 2)];
-      return (j >= 1 && j < N) ? x : 0.0;
-    });
-  } else {
-#pragma unroll
-    for (int t = 0; t < RL; ++t) {
-      const int e = q + t * P;
-      double v[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int i = 2 * e + h;
-        const int m = i < M ? 2 * i : 2 * N - 2 * i - 1;
-        v[h] = (m & 1) ? -cv[m] : cv[m];
-      }
-      a[t] = make_double2(v[0], v[1]);
-    }
-  }
-  __syncthreads();  // the staged input is read before the first pass overwrites it
-  if constexpr (ODD) {
-    fft_passes<M, -1, 1>(a, Z, q, d.cs);
-    dst1_post<M>(Z, cv, q, d.cs);
-  } else {
-    fft_passes<M, -1, 1>(a, Z, q, d.cs);
-    dst2_post<M>(Z, cv, q, d.cs, d.tq);
-  }
-  double* zc = Zo + (long long)c * d.n;
-  const auto rz = buf_rsrc(Zo + (long long)c0 * d.n, (long long)B * d.n), rg = buf_rsrc(d.g, d.n1);
-#pragma unroll
-  for (int u = 0; u < 2 * RL; ++u) {
-    const int mm = q + P * u;
-    const bool ok = valid && mm < d.n1;
-    buf_st(rz, b * d.n + mm, ok, buf_ld(rg, mm, ok) * cv[mm]);
-  }
-  for (int a2 = 0; a2 < d.n2; ++a2) {
-    const double* v2 = d.v2u2 + (long long)a2 * d.n;
-    const auto rv = buf_rsrc(v2, d.n);
-    double part = 0.0;
-#pragma unroll
-    for (int u = 0; u < 2 * RL; ++u) {
-      const int i = q + P * u;
-      const bool ok = i < d.n;
-      part += buf_ld(rv, i, ok) * buf_ld(rs, sb + i, ok && valid);
-    }
-    for (int i = N + q; i < d.n; i += P) part += v2[i] * s[i];
-    part = seg_sum<P>(part);
-    if (valid && q == 0) zc[d.n1 + a2] = part;
-  }
-}
-
-// Y[:, j r + c] = U~ D_j Z[:, c] (Algorithm 4, steps 7-8) for j in this
-// workgroup's range: the scaled coefficients staged in LDS, the inverse sine
-// transform, then E and the V_2 columns.
-template <int M, bool ODD>
-__global__ __launch_bounds__(kFdWave) void k_fd_backward(FdDev d, const double* __restrict__ Zi, int r,
-                                                         double* __restrict__ Y) {
-  constexpr int N = 2 * M, RL = FdShape<M>::RL, P = FdShape<M>::P, B = FdShape<M>::B;
-  constexpr int SL = FdSlot<M>::SIZE;
-  __shared__ double2 sm[B * SL];
-  const int lane = threadIdx.x, b = lane / P, q = lane % P;
-  // the R_P terms of one column run in consecutive logical workgroups on one
-  // XCD (the column is then read from that XCD's L2 after the first)
-  const int nj = (d.R + B - 1) / B;
-  const int lb = xcd_order(blockIdx.x, gridDim.x);
-  const int c = lb / nj, jg = lb - c * nj;
-  const int j = jg * B + b;
-  const bool valid = j < d.R;
-  const double* zc = Zi + (long long)c * d.n;
-  const CBuf Z{sm + b * SL};
-  const RBuf cv{reinterpret_cast<double*>(sm + b * SL)};
-  {
-    const double* ge = d.ge + (long long)(valid ? j : d.R - 1) * d.n;
-    const auto rg = buf_rsrc(d.ge, (long long)d.R * d.n), rz = buf_rsrc(zc, d.n);
-    const int gb = (valid ? j : 0) * d.n;
-    // w_m = ge_m z_m for m < N (for odd p the entry m = n1 = N - 1 is a V_2
-    // coefficient the transform never reads)
-#pragma unroll
-    for (int u = 0; u < 2 * RL; ++u) {
-      const int m = q + P * u;
-      const bool ok = m < d.n;
-      cv[m] = buf_ld(rg, gb + m, ok) * buf_ld(rz, m, ok);
-    }
-    double w2[kFdMaxV2];
-#pragma unroll
-    for (int a2 = 0; a2 < kFdMaxV2; ++a2) {
-      const bool ok = a2 < d.n2;
-      w2[a2] = buf_ld(rg, gb + d.n1 + a2, ok) * buf_ld(rz, d.n1 + a2, ok);
-    }
-    __syncthreads();
-    double2 a[RL];
-    if constexpr (ODD) {
-      dst1_pre<M>(a, q, d.sn, [&](int jj) {
-        const double x = cv[min(max(jj - 1, 0), N - 2)];
-        return (jj >= 1 && jj < N) ? x : 0.0;
-      });
-    } else {
-      // inverse of the DST-II steps on S_s = w_{s-1}, the last one doubled
-#pragma unroll
-      for (int t = 0; t < RL; ++t) {
-        const int k = q + t * P, km = M - k, k1 = max(k, 1);
-        const double sN = cv[N - 1], sa = cv[N - k1 - 1], sb = cv[k1 - 1];
-        const double2 qk = k == 0 ? make_double2(2.0 * sN, 0.0) : make_double2(sa, -sb);
-        const double2 qm = make_double2(cv[N - km - 1], -cv[km - 1]);
-        const double2 vk = c_mul(c_conj(d.tq[k]), qk), vm = c_conj(c_mul(c_conj(d.tq[km]), qm));
-        const double2 e = make_double2(0.5 * (vk.x + vm.x), 0.5 * (vk.y + vm.y));
-        const double2 o = c_mul(make_double2(0.5 * (vk.x - vm.x), 0.5 * (vk.y - vm.y)), c_conj(d.cs[k]));
-        a[t] = make_double2(e.x - o.y, e.y + o.x);  // e + i o
-      }
-    }
-    __syncthreads();  // the staged input is read before the first pass overwrites it
-    if constexpr (ODD) {
-      fft_passes<M, -1, 1>(a, Z, q, d.cs);
-      dst1_post<M>(Z, cv, q, d.cs);
-    } else {
-      fft_passes<M, 1, 1>(a, Z, q, d.cs);
-      // v = the FFT output read as N reals (v_{2i} = Re z_i, v_{2i+1} = Im z_i);
-      // T_m = (-1)^m v[m even ? m/2 : N-1-(m-1)/2]
-      double tv[2 * RL];
-#pragma unroll
-      for (int u = 0; u < 2 * RL; ++u) {
-        const int m = q + P * u;
-        const int i = (m & 1) ? N - 1 - (m >> 1) : (m >> 1);
-        const double2 zi = Z[i >> 1];
-        const double x = (i & 1) ? zi.y : zi.x;
-        tv[u] = (m & 1) ? -x : x;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 2 * RL; ++u) cv[q + P * u] = tv[u];
-      __syncthreads();
-    }
-    double* yc = Y + ((long long)(valid ? j : 0) * r + c) * d.n;
-    auto v2 = [&](int l) {
-      double acc = 0.0;
-#pragma unroll
-      for (int a2 = 0; a2 < kFdMaxV2; ++a2)
-        if (a2 < d.n2) acc += d.v2u2[l + (long long)a2 * d.n] * w2[a2];
-      return acc;
-    };
-    // interior rows of E (a shifted copy): at most N = 2 RL P, 2 RL per lane,
-    // the loads clamped into range so that they issue together
-    if (d.e_hi > d.e_lo) {  // uniform
-      // the B output columns of the workgroup (stride r n) through one resource
-      const int j0 = jg * B;
-      const auto ry = buf_rsrc(Y + ((long long)j0 * r + c) * d.n, ((long long)(B - 1) * r + 1) * d.n);
-      const int yb = b * r * d.n;
-      double acc[2 * RL];
-#pragma unroll
-      for (int u = 0; u < 2 * RL; ++u) acc[u] = cv[min(d.e_lo + q + P * u, d.e_hi - 1) + d.e_sh];
-#pragma unroll
-      for (int a2 = 0; a2 < kFdMaxV2; ++a2) {
-        if (a2 < d.n2) {  // uniform
-          const auto rv = buf_rsrc(d.v2u2 + (long long)a2 * d.n, d.n);
-#pragma unroll
-          for (int u = 0; u < 2 * RL; ++u) acc[u] += buf_ld(rv, d.e_lo + q + P * u, true) * w2[a2];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 2 * RL; ++u) {
-        const int l = d.e_lo + q + P * u;
-        buf_st(ry, yb + l, valid && l < d.e_hi, acc[u]);
-      }
-    }
-    // boundary rows [0, e_lo) and [e_hi, n) through the ELL table
-    auto ell = [&](int l) {
-      double acc = 0.0;
-      for (int k = 0; k < d.ke; ++k) {
-        const int src = d.e_idx[l * d.ke + k];
-        if (src >= 0) acc += d.e_val[l * d.ke + k] * cv[src];
-      }
-      if (valid) yc[l] = acc + v2(l);
-    };
-    for (int l = q; l < d.e_lo; l += P) ell(l);
-    for (int l = d.e_hi + q; l < d.n; l += P) ell(l);
-  }
-}
-
-// the kernels address a workgroup's columns with 32-bit byte offsets
-static void fd_check_span(long long doubles, const char* what) {
-  if (doubles * 8 >= (long long)kBufOffHost) throw std::runtime_error(std::string(what) + ": more than 4 GB in one workgroup's reach");
-}
-
-template <int M>
-static void fd_forward_m(hipStream_t s, const FdDev& d, const double* S, int lds_, int r, double* Z) {
-  constexpr int B = FdShape<M>::B;
-  fd_check_span((long long)B * lds_ + d.n, "fd_forward");
-  const dim3 grid((r + B - 1) / B);
-  if (d.odd)
-    hipLaunchKernelGGL((k_fd_forward<M, true>), grid, dim3(kFdWave), 0, s, d, S, lds_, r, Z);
-  else
-    hipLaunchKernelGGL((k_fd_forward<M, false>), grid, dim3(kFdWave), 0, s, d, S, lds_, r, Z);
-}
-
-template <int M>
-static void fd_backward_m(hipStream_t s, const FdDev& d, const double* Z, int r, double* Y) {
-  constexpr int B = FdShape<M>::B;
-  fd_check_span((long long)B * r * d.n + (long long)d.R * d.n, "fd_backward");
-  const dim3 grid((unsigned)r * ((d.R + B - 1) / B));
-  if (d.odd)
-    hipLaunchKernelGGL((k_fd_backward<M, true>), grid, dim3(kFdWave), 0, s, d, Z, r, Y);
-  else
-    hipLaunchKernelGGL((k_fd_backward<M, false>), grid, dim3(kFdWave), 0, s, d, Z, r, Y);
-}
-
-#define TK_FD_DISPATCH(FN, ...)                                            \
-  switch (d.N) {                                                           \
-    case 4: FN<2>(__VA_ARGS__); break;                                     \
-    case 8: FN<4>(__VA_ARGS__); break;                                     \
-    case 16: FN<8>(__VA_ARGS__); break;                                    \
-    case 32: FN<16>(__VA_ARGS__); break;                                   \
-    case 64: FN<32>(__VA_ARGS__); break;                                   \
-    case 128: FN<64>(__VA_ARGS__); break;                                  \
-    case 256: FN<128>(__VA_ARGS__); break;                                 \
-    case 512: FN<256>(__VA_ARGS__); break;                                 \
-    case 1024: FN<512>(__VA_ARGS__); break;                                \
-    default: throw std::runtime_error("fd: transform length must be a power of two in [4, 1024]"); \
-  }
-
-void fd_forward(hipStream_t s, const FdDev& d, const double* S, int lds_, int r, double* Z) {
-  if (r <= 0) return;
-  if (d.n2 > kFdMaxV2) throw std::runtime_error("fd_forward: more than 4 V_2 columns (degree above 6)");
-  TK_FD_DISPATCH(fd_forward_m, s, d, S, lds_, r, Z);
-  check_launch("fd_forward");
-}
-
-void fd_backward(hipStream_t s, const FdDev& d, const double* Z, int r, double* Y) {
-  if (r <= 0 || d.R <= 0) return;
-  if (d.n2 > kFdMaxV2) throw std::runtime_error("fd_backward: more than 4 V_2 columns (degree above 6)");
-  if (d.R > 65535) throw std::runtime_error("fd_backward: more than 65535 exponential-sum terms");
-  TK_FD_DISPATCH(fd_backward_m, s, d, Z, r, Y);
-  check_launch("fd_backward");
 }
 
 }  // namespace gpu
