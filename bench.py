@@ -27,6 +27,7 @@ Prints one JSON line (see the "metric" key) with:
   cpu_baseline         the FP64 oracle on the host cores (bounded sample)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload deformed|small]
+                       [--fd approx|exact] [--no-hbm] [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -114,8 +115,16 @@ def mode_products_hbm(ctx, reps=5):
     ev1.record()
     torch.cuda.synchronize()
     copy_gbs = 2.0 * src.numel() * 8 * reps / (ev0.elapsed_time(ev1) / 1e3) / 1e9
+    # write-only reference (the two mode-product kernels are ~90 % writes)
+    ev0.record()
+    for _ in range(reps):
+        dst.fill_(2.0)
+    ev1.record()
+    torch.cuda.synchronize()
+    fill_gbs = dst.numel() * 8 * reps / (ev0.elapsed_time(ev1) / 1e3) / 1e9
     del src, dst
     out["copy_probe"] = {"bytes_per_copy": 2 * (1 << 28) * 8, "GB_s": copy_gbs, "frac": copy_gbs / PEAK_HBM_GBS}
+    out["fill_probe"] = {"bytes_per_fill": (1 << 28) * 8, "GB_s": fill_gbs, "frac": fill_gbs / PEAK_HBM_GBS}
     w, core, U = k1_inputs()
     op = problem.operator(ctx, w)
     x = tk.Tucker.from_host(ctx, core, U)
@@ -170,7 +179,7 @@ def mode_products_hbm(ctx, reps=5):
     return out
 
 
-def cpu_baseline(w, gpu_iters, target_s=12.0):
+def cpu_baseline(w, gpu_iters, target_s=12.0, exact=False):
     """The oracle's TPCG (unchanged) on a bounded sample of the same solve:
     the first k TPCG iterations (including the initial preconditioner and
     operator truncations), k chosen from a one-iteration calibration run so
@@ -182,7 +191,7 @@ def cpu_baseline(w, gpu_iters, target_s=12.0):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     op = oprob.operator(w)
     f = oprob.rhs(w)
-    prec = ofd.LowRankFD(w.n_el, w.p, 0.1)
+    prec = ofd.LowRankFD(w.n_el, w.p, 0.1, exact=exact)
     t0 = time.perf_counter()
     otpcg.tpcg(op, prec, f, tol=w.tol, eps_min=w.eps_min, maxit=1)
     t1 = time.perf_counter() - t0
@@ -209,6 +218,9 @@ def main():
     ap.add_argument("--workload", default="deformed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm", action="store_true", help="skip the batched mode-product bandwidth runs")
+    ap.add_argument("--fd", choices=("approx", "exact"), default="approx",
+                    help="preconditioner eigenpairs: Appendix B approximations applied by sine transforms "
+                         "(default) or the exact generalized eigenpairs applied by dense GEMMs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of MIB MiB (read + write) before the solves, "
                          "as the known-size reference of a rocprofv3 FETCH_SIZE/WRITE_SIZE run")
@@ -234,7 +246,7 @@ def main():
         del src, dst
     ctx = tk.Context(0)
     op = problem.operator(ctx, w)
-    prec = problem.preconditioner(ctx, w)
+    prec = problem.preconditioner(ctx, w, exact=(args.fd == "exact"))
     f = problem.rhs(ctx, w)
     params = dict(tol=w.tol, eps_min=w.eps_min)
     for _ in range(args.warmup):
@@ -306,7 +318,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_el": w.n_el, "p": w.p, "dofs_per_direction": w.n,
+        "config": {"workload": w.name, "fd_eigenpairs": args.fd, "n_el": w.n_el, "p": w.p, "dofs_per_direction": w.n,
                    "kronecker_terms": len(w.nnz), "rhs_rank": int(np.asarray(problem.rhs_arrays(w)[0]).shape[0]),
                    "tol": w.tol, "iters": last_info["iters"], "relres": last_info["relres"],
                    "solution_rank": list(last_info["rank"]), "trel_calls": last_info["trel_calls"]},
@@ -320,7 +332,7 @@ def main():
     if not args.no_hbm:
         out["mode_products_hbm"] = mode_products_hbm(ctx)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
-        out["cpu_baseline"] = cpu_baseline(w, last_info["iters"])
+        out["cpu_baseline"] = cpu_baseline(w, last_info["iters"], exact=(args.fd == "exact"))
     print(json.dumps(out), flush=True)
 
 

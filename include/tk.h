@@ -159,6 +159,20 @@ tk_status tucker_apply_op(tk_ctx* ctx, const tk_op* op, const tk_tucker* x, tk_t
  * be a power of two in [4, 1024] with n_el[k] > p.  `R_P` may be NULL. */
 tk_status fd_setup(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec,
                    const double coef[3], tk_prec** out, int32_t* R_P);
+
+/* Exact-eigenvector variant (Algorithm 4 with the factorizations of
+ * Algorithm 3, eq. factorizations; the check of Sec. 5's remark on exact
+ * eigenpairs): the generalized eigenpairs of (coef[k] K, M) of each direction
+ * are computed at setup (C = L^{-1} K L^{-T} with M = L L^T, diagonalized by
+ * the library's symmetric eigensolver, U = L^{-T} Q), kept on the device as
+ * dense M-orthonormal n x n matrices, and applied by fd_precond as two
+ * matrix-core GEMMs per mode (U^T S, then U [D_1 Z, ..., D_R Z]).  The
+ * exponential sum and everything else as fd_setup.  n_el[k] in (p, 4096];
+ * no power-of-two restriction.  Setup costs O(n^3) per direction on the
+ * device; the dense U take 8 n^2 bytes per direction.  EINVAL on bad
+ * arguments, ENUMERIC if an eigenvalue is not positive. */
+tk_status fd_setup_exact(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec,
+                         const double coef[3], tk_prec** out, int32_t* R_P);
 void tk_prec_free(tk_prec* P);
 
 /* R_P, lambda_min, lambda_max, E_{R_P}(M_P); alpha/omega (R_P doubles each,
@@ -167,12 +181,17 @@ tk_status tk_prec_info(const tk_prec* P, int32_t* R_P, double* lam_min, double* 
                        double* err, double* alpha, double* omega);
 
 /* v = P~^{-1} s (eq. prec), untruncated: factors [U~ D_(k,1) U~^T S_k, ...],
- * core P (x) S as R_P blocks with weights omega_j/lambda_min.  U~ is applied
- * by DST passes in LDS (no dense eigenvector matrix).  Asynchronous. */
+ * core P (x) S as R_P blocks with weights omega_j/lambda_min.  For a
+ * preconditioner from fd_setup U~ is applied by sine transforms (no dense
+ * eigenvector matrix); from fd_setup_exact by GEMMs with the dense exact U.
+ * Asynchronous. */
 tk_status fd_precond(tk_ctx* ctx, const tk_prec* P, const tk_tucker* s, tk_tucker** v);
 
 /* Appendix B data of direction k for inspection (host, caller-owned):
- * lam (n), g (n1), E (n x n1 dense, column-major), v2u2 (n x n2). Any may be NULL. */
+ * lam (n), g (n1), E (n x n1 dense, column-major), v2u2 (n x n2). Any may be NULL.
+ * For a preconditioner from fd_setup_exact: n, n1 = n, n2 = 0 and lam (the
+ * exact eigenvalues, in the eigensolver's descending order); g, E and v2u2
+ * are left untouched. */
 tk_status tk_prec_direction(const tk_prec* P, int32_t k, int32_t* n, int32_t* n1, int32_t* n2,
                             double* lam, double* g, double* E, double* v2u2);
 

@@ -18,9 +18,13 @@ Appendix B (Dirichlet at both ends) is built densely, as written:
   V_h2 = M-orthogonal complement of V_h1 with its exact small eigenproblem.
 Readings (listed in DESIGN.md):
 * "C^{-1} U_dft" is the interpolation in V_h1 of the sampled sines (the
-  coefficients a with sum_i a_i v_i(x_j) = U_dft[j, :]); the sqrt(2) is applied
-  once, so the interpolated sines have unit L2 norm like M-orthonormal
-  eigenvectors;
+  coefficients a with sum_i a_i v_i(x_j) = U_dft[j, :]);
+* "normalized in the L^2 norm": every approximate eigenvector function (a
+  column of V1 U1) is scaled to unit L^2 norm, i.e. unit M-norm, as the exact
+  ones of eq. factorizations (U^T M U = I); the printed factors sqrt(2) then
+  play no role.  With this reading exact and approximate eigenpairs give
+  nearly the same TPCG iteration counts, as the remark in Sec. 5 states
+  (25 against 12 iterations at n_el = 32, p = 2 without the scaling);
 * the M-orthogonal complement of ker(D) is spanned by V2 = M^{-1} D^T, where
   D holds the even-derivative constraints;
 * for p = 2 (n2 = 0) the same sine construction is used; it reproduces the
@@ -89,6 +93,15 @@ def _constraints(n_el, p, at):
     return np.array(rows).reshape(-1, n)
 
 
+def exact_eig(n_el: int, p: int):
+    """(U, Lambda) of eq. factorizations for one direction: K U = M U Lambda,
+    U^T M U = I, with the parametric 1D stiffness and mass (Dirichlet space)."""
+    K = bspline.matrix(n_el, p, "stiff")
+    M = bspline.matrix(n_el, p, "mass")
+    lam, U = sla.eigh(K, M)
+    return U, lam
+
+
 def approx_eig(n_el: int, p: int):
     """(U~, Lambda~, parts) of Appendix B for one direction.
 
@@ -123,17 +136,20 @@ def approx_eig(n_el: int, p: int):
     jj = np.arange(1, n1 + 1)
     Udft = np.sqrt(2.0) * np.sin(np.pi * np.outer(x, jj))   # [U_dft]_{i,j}
     U1 = np.linalg.solve(C.T, Udft)                  # interpolation in V_h1
+    # unit L^2 (= M) norm of every interpolated sine
+    W1 = V1 @ U1
+    scale1 = 1.0 / np.sqrt(np.einsum("ij,ij->j", W1, M @ W1))
     parts = {"V1": V1, "C": C, "Udft": Udft, "U1": U1, "D": D, "K": K, "M": M,
-             "x": x, "n1": n1, "n2": n2}
+             "x": x, "n1": n1, "n2": n2, "scale1": scale1}
     lam1 = (np.pi * jj) ** 2
     if n2 > 0:
         V2 = np.linalg.solve(M, D.T)                 # M-orthogonal complement
         lam2, U2 = sla.eigh(V2.T @ K @ V2, V2.T @ M @ V2)
         parts.update(V2=V2, U2=U2, lam2=lam2)
-        Ut = np.hstack([V1 @ U1, V2 @ U2])
+        Ut = np.hstack([W1 * scale1, V2 @ U2])
         lam = np.concatenate([lam1, lam2])
     else:
-        Ut = V1 @ U1
+        Ut = W1 * scale1
         lam = lam1
     return Ut, lam, parts
 
@@ -144,18 +160,22 @@ def approx_eig(n_el: int, p: int):
 
 class LowRankFD:
     """P~^{-1} = (1/lambda_min) (U~3 x U~2 x U~1) (sum_j omega_j D3j x D2j x D1j)
-    (U~3 x U~2 x U~1)^T (eq. prec).
+    (U~3 x U~2 x U~1)^T (eq. prec); with exact=True the eigenpairs are the
+    exact ones of eq. factorizations instead of Appendix B's.
 
     `coef` scales the approximate eigenvalues of each direction (block
     preconditioners with direction coefficients); `expsum_table` may hold
     precomputed (R_P, alpha, omega) for this M_P."""
 
-    def __init__(self, n_el, p, eps_prec=0.1, coef=(1.0, 1.0, 1.0), expsum_table=None):
+    def __init__(self, n_el, p, eps_prec=0.1, coef=(1.0, 1.0, 1.0), expsum_table=None, exact=False):
         self.Ut, self.lam = [], []
         if np.isscalar(n_el):
             n_el = (n_el,) * 3
         for i in range(3):
-            U, lam, _ = approx_eig(n_el[i], p)
+            if exact:   # Algorithm 4 with the exact factorizations of Algorithm 3
+                U, lam = exact_eig(n_el[i], p)
+            else:
+                U, lam, _ = approx_eig(n_el[i], p)
             self.Ut.append(U)
             self.lam.append(coef[i] * lam)
         self.lam_min = sum(np.min(l) for l in self.lam)

@@ -101,6 +101,9 @@ struct FdDev {
 void fd_forward(hipStream_t s, const FdDev& d, const double* S, int lds, int r, double* Z);
 // Y[:, j*r + c] = U~ D_j Z[:, c] for j < R, c < r  (Y ld = n)
 void fd_backward(hipStream_t s, const FdDev& d, const double* Z, int r, double* Y);
+// exact-eigenvector variant: W[:, j r + c] = E[j, :] .* Z[:, c] (E: R x n, row j
+// at E + j n; Z: n x r; W: n x R r)
+void fd_exact_scale(hipStream_t s, int n, int r, int R, const double* E, const double* Z, double* W);
 
 }  // namespace gpu
 }  // namespace tk

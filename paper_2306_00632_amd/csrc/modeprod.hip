@@ -73,7 +73,8 @@ __global__ __launch_bounds__(kBandRows) void k_band_apply(int n, int m, int nmat
       double acc = 0.0;
 #pragma unroll
       for (int o = 0; o < NB; ++o) acc += bv[o] * yw[o];
-      if (cc < nc) W[i + (long long)(t * m + c0 + cc) * ldw] = acc;
+      // streaming store: the R outputs are written once and read by later kernels
+      if (cc < nc) __builtin_nontemporal_store(acc, W + i + (long long)(t * m + c0 + cc) * ldw);
     }
 #pragma unroll
     for (int o = 0; o < NB; ++o) bv[o] = bnext[o];
@@ -639,6 +640,31 @@ void fd_backward(hipStream_t s, const FdDev& d, const double* Z, int r, double* 
   if (d.R > 65535) throw std::runtime_error("fd_backward: more than 65535 exponential-sum terms");
   TK_FD_DISPATCH(fd_backward_m, s, d, Z, r, Y);
   check_launch("fd_backward");
+}
+
+// ---------------------------------------------------------------------------
+// exact-eigenvector FD (Algorithm 4 with the factorizations of Algorithm 3)
+// ---------------------------------------------------------------------------
+
+// W[:, j r + c] = E[j, :] .* Z[:, c] for j < R, c < r (n rows); the dense
+// products with U before and after are matrix-core GEMMs
+__global__ __launch_bounds__(256) void k_fd_exact_scale(int n, int r, int R, const double* __restrict__ E,
+                                                        const double* __restrict__ Z, double* __restrict__ W) {
+  const long long total = (long long)n * r * R;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x) {
+    const int m = (int)(e % n);
+    const long long col = e / n;  // j r + c
+    const int j = (int)(col / r), c = (int)(col - (long long)j * r);
+    W[e] = E[(long long)j * n + m] * Z[(long long)c * n + m];
+  }
+}
+
+void fd_exact_scale(hipStream_t s, int n, int r, int R, const double* E, const double* Z, double* W) {
+  if (n <= 0 || r <= 0 || R <= 0) return;
+  const long long total = (long long)n * r * R;
+  const int nb = (int)std::min<long long>(4096, (total + 255) / 256);
+  hipLaunchKernelGGL(k_fd_exact_scale, dim3(nb), dim3(256), 0, s, n, r, R, E, Z, W);
+  check_launch("fd_exact_scale");
 }
 
 }  // namespace gpu

@@ -160,6 +160,12 @@ struct tk_prec {
   tk::BufP g[3], e_val[3], et_val[3], v2u2[3], ge[3], cs[3], sn[3], tq[3];
   tk::BufP e_idx[3], et_idx[3];  // stored as ints inside double buffers
   tk::gpu::FdDev dev[3];
+  // exact-eigenvector variant (fd_setup_exact): dense M-orthonormal U_k
+  // (n_k x n_k) and E_k[j, m] = exp(-alpha_j lam_m / lam_min) (R x n_k)
+  bool exact = false;
+  int n_exact[3] = {0, 0, 0};
+  std::vector<double> lam_exact[3];
+  tk::BufP Ud[3], Ed[3];
 };
 
 namespace tk {
@@ -638,9 +644,35 @@ static tk_tucker* apply_op(tk_ctx* ctx, const tk_op* op, const tk_tucker* x) {
 static tk_tucker* apply_prec(tk_ctx* ctx, const tk_prec* P, const tk_tucker* s) {
   if (s->blocks.size() != 1) throw Error(TK_EINVAL, "fd_precond expects a plain (truncated) Tucker tensor");
   for (int k = 0; k < 3; ++k)
-    if (s->n[k] != P->dir[k].n) throw Error(TK_EINVAL, "preconditioner and tensor sizes differ");
+    if (s->n[k] != (P->exact ? P->n_exact[k] : P->dir[k].n))
+      throw Error(TK_EINVAL, "preconditioner and tensor sizes differ");
   auto* t = new tk_tucker;
   const Block& sb = s->blocks[0];
+  if (P->exact) {
+    // Y_(k,j) = U_k D_(k,j) U_k^T S_k: Z = U^T S, W = [D_j Z]_j, Y = U W
+    for (int k = 0; k < 3; ++k) {
+      const int n = s->n[k], r = s->m[k];
+      t->n[k] = n;
+      t->m[k] = P->R * r;
+      t->U[k] = alloc(ctx, (size_t)n * t->m[k]);
+      if (r == 0) continue;
+      BufP Z = alloc(ctx, (size_t)n * r), W = alloc(ctx, (size_t)n * t->m[k]);
+      gemm(ctx, true, false, n, r, n, 1.0, P->Ud[k]->p, n, s->U[k]->p, n, 0.0, Z->p, n);
+      {
+        Prof pr(ctx, PK_FD_BWD, 8.0 * ((double)n * r + (double)P->R * n + (double)P->R * n * r),
+                (double)P->R * n * r);
+        gpu::fd_exact_scale(ctx->stream, n, r, P->R, P->Ed[k]->p, Z->p, W->p);
+      }
+      gemm(ctx, false, false, n, t->m[k], n, 1.0, P->Ud[k]->p, n, W->p, n, 0.0, t->U[k]->p, n);
+    }
+    for (int j = 0; j < P->R; ++j) {
+      Block c = sb;
+      c.c = sb.c * P->omega[j] / P->lam_min;
+      for (int k = 0; k < 3; ++k) c.off[k] = j * s->m[k] + sb.off[k];
+      t->blocks.push_back(c);
+    }
+    return t;
+  }
   for (int k = 0; k < 3; ++k) {
     const int n = s->n[k], r = s->m[k];
     t->n[k] = n;
@@ -1334,6 +1366,59 @@ tk_status fd_setup(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_pre
   });
 }
 
+tk_status fd_setup_exact(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec, const double coef[3],
+                         tk_prec** out, int32_t* R_P) {
+  if (!ctx || !n_el || !out || !(eps_prec > 0.0)) return TK_EINVAL;
+  *out = nullptr;
+  return guarded(ctx, [&]() {
+    std::unique_ptr<tk_prec> P(new tk_prec);
+    P->exact = true;
+    std::string msg;
+    std::vector<double> L[3];
+    for (int k = 0; k < 3; ++k) {
+      const double c = coef ? coef[k] : 1.0;
+      if (!(c > 0.0)) throw Error(TK_EINVAL, "fd_setup_exact: direction coefficients must be positive");
+      std::vector<double> C;
+      int n = 0;
+      if (!fd_exact_pencil(n_el[k], p, c, C, L[k], n, msg)) throw Error(TK_EINVAL, msg);
+      P->n_exact[k] = n;
+      // eigenpairs of C with the library's symmetric eigensolver
+      BufP Cd = alloc(ctx, (size_t)n * n), V = alloc(ctx, (size_t)n * n), w = alloc(ctx, (size_t)n);
+      BufP work = alloc(ctx, gpu::sym_eig_work(n));
+      h2d(ctx, Cd->p, C.data(), (size_t)n * n);
+      gpu::sym_eig(ctx->stream, Cd->p, n, V->p, w->p, work->p);
+      std::vector<double> Q = d2h(ctx, V->p, (size_t)n * n);
+      P->lam_exact[k] = d2h(ctx, w->p, (size_t)n);
+      for (double v : P->lam_exact[k])
+        if (!(v > 0.0)) throw Error(TK_ENUMERIC, "fd_setup_exact: non-positive eigenvalue");
+      fd_exact_vectors(L[k], n, p, Q.data());  // U = L^{-T} Q, M-orthonormal
+      P->Ud[k] = alloc(ctx, (size_t)n * n);
+      h2d(ctx, P->Ud[k]->p, Q.data(), (size_t)n * n);
+      const auto& l = P->lam_exact[k];
+      P->lam_min += *std::min_element(l.begin(), l.end());
+      P->lam_max += *std::max_element(l.begin(), l.end());
+    }
+    ExpSum es;
+    if (!expsum_for(P->lam_max / P->lam_min, eps_prec, es, msg)) throw Error(TK_ENUMERIC, msg);
+    P->R = es.R;
+    P->alpha = es.alpha;
+    P->omega = es.omega;
+    P->err = es.err;
+    P->err_prev = es.err_prev;
+    for (int k = 0; k < 3; ++k) {
+      const int n = P->n_exact[k];
+      std::vector<double> E((size_t)P->R * n);
+      for (int j = 0; j < P->R; ++j)
+        for (int m = 0; m < n; ++m) E[(size_t)j * n + m] = std::exp(-P->alpha[j] * P->lam_exact[k][m] / P->lam_min);
+      P->Ed[k] = alloc(ctx, E.size());
+      h2d(ctx, P->Ed[k]->p, E.data(), E.size());
+    }
+    if (R_P) *R_P = P->R;
+    *out = P.release();
+    return TK_OK;
+  });
+}
+
 void tk_prec_free(tk_prec* P) { delete P; }
 
 tk_status tk_prec_info(const tk_prec* P, int32_t* R_P, double* lam_min, double* lam_max, double* err,
@@ -1353,6 +1438,14 @@ tk_status tk_prec_info(const tk_prec* P, int32_t* R_P, double* lam_min, double* 
 tk_status tk_prec_direction(const tk_prec* P, int32_t k, int32_t* n, int32_t* n1, int32_t* n2, double* lam,
                             double* g, double* E, double* v2u2) {
   if (!P || k < 0 || k > 2) return TK_EINVAL;
+  if (P->exact) {
+    const int ne = P->n_exact[k];
+    if (n) *n = ne;
+    if (n1) *n1 = ne;
+    if (n2) *n2 = 0;
+    if (lam) std::copy(P->lam_exact[k].begin(), P->lam_exact[k].end(), lam);
+    return TK_OK;
+  }
   const auto& d = P->dir[k];
   if (n) *n = d.n;
   if (n1) *n1 = d.n1;
@@ -1444,7 +1537,7 @@ static bool block_args_ok(const tk_op* const A[9], const tk_prec* const P[3], co
     for (int a = 0; a < 3; ++a) {
       if (!P[a]) return false;
       for (int k = 0; k < 3; ++k)
-        if (P[a]->dir[k].n != v[0]->n[k]) return false;
+        if ((P[a]->exact ? P[a]->n_exact[k] : P[a]->dir[k].n) != v[0]->n[k]) return false;
     }
   }
   return true;

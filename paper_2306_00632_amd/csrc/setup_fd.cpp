@@ -308,6 +308,36 @@ bool fd_direction_setup(int n_el, int p, double coef, FdDirection& d, std::strin
       }
   }
 
+  // unit L^2 norm (M-norm) of every approximate eigenvector function: column
+  // k of V1 U1 is g_k E s_k with s_k the sine vector of the transform (DST-I
+  // samples sin(pi j k / N) for odd p, DST-II samples sin(pi (2m+1) k / 2N)
+  // for even p), so g_k becomes sign(g_k) / ||E s_k||_M
+  {
+    const double unit[4] = {1.0, 0.0, 0.0, 0.0};
+    std::vector<double> Mb(size_t(2 * p + 1) * n), sk(n1), v(n), Mv(n);
+    assemble_band(n_el, p, 0, unit, Mb.data());
+    for (int k = 1; k <= n1; ++k) {
+      for (int m = 0; m < n1; ++m)
+        sk[m] = d.odd ? std::sin(kPi * double(m + 1) * k / N) : std::sin(kPi * double(2 * m + 1) * k / (2.0 * N));
+      for (int i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int c = 0; c < ke; ++c) {
+          const int j = d.e_idx[size_t(i) * ke + c];
+          if (j >= 0) acc += d.e_val[size_t(i) * ke + c] * sk[j];
+        }
+        v[i] = acc;
+      }
+      band_matvec(Mb, n, p, v.data(), Mv.data());
+      double nrm2 = 0.0;
+      for (int i = 0; i < n; ++i) nrm2 += v[i] * Mv[i];
+      if (!(nrm2 > 0.0)) {
+        msg = "fd_setup: interpolated sine with zero norm";
+        return false;
+      }
+      d.g[k - 1] = (d.g[k - 1] >= 0.0 ? 1.0 : -1.0) / std::sqrt(nrm2);
+    }
+  }
+
   // eigenvalue approximations on V_h1
   d.lam.assign(n, 0.0);
   for (int j = 1; j <= n1; ++j) d.lam[j - 1] = coef * (kPi * j) * (kPi * j);
@@ -399,6 +429,70 @@ bool fd_direction_setup(int n_el, int p, double coef, FdDirection& d, std::strin
     }
   }
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// exact eigenpairs (Algorithm 3's factorizations) for the exact-FD variant
+// ---------------------------------------------------------------------------
+
+bool fd_exact_pencil(int n_el, int p, double coef, std::vector<double>& C, std::vector<double>& L, int& n,
+                     std::string& msg) {
+  if (p < 1 || n_el <= p || n_el > 4096) {
+    msg = "fd_setup_exact: need p >= 1 and p < n_el <= 4096";
+    return false;
+  }
+  n = n_el + p - 2;
+  const double unit[4] = {1.0, 0.0, 0.0, 0.0};
+  std::vector<double> Mb(size_t(2 * p + 1) * n), Kb(size_t(2 * p + 1) * n);
+  assemble_band(n_el, p, 0, unit, Mb.data());
+  assemble_band(n_el, p, 1, unit, Kb.data());
+  if (!band_cholesky(Mb, n, p, L)) {
+    msg = "fd_setup_exact: mass matrix not positive definite";
+    return false;
+  }
+  auto lower_solve = [&](double* x) {  // x <- L^{-1} x
+    for (int i = 0; i < n; ++i) {
+      double s = x[i];
+      for (int k = std::max(0, i - p); k < i; ++k) s -= L[size_t(i) * (p + 1) + (i - k)] * x[k];
+      x[i] = s / L[size_t(i) * (p + 1)];
+    }
+  };
+  // X = L^{-1} (coef K), column by column (K symmetric, banded)
+  std::vector<double> X(size_t(n) * n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    double* col = X.data() + size_t(c) * n;
+    for (int o = -p; o <= p; ++o) {
+      const int r = c - o;  // K[r, c] = band[(c - r + p) n + r]
+      if (r >= 0 && r < n) col[r] = coef * Kb[size_t(o + p) * n + r];
+    }
+    lower_solve(col);
+  }
+  // C = L^{-1} X^T (= L^{-1} K L^{-T}), then symmetrized
+  C.assign(size_t(n) * n, 0.0);
+  std::vector<double> tmp(n);
+  for (int c = 0; c < n; ++c) {
+    for (int r = 0; r < n; ++r) tmp[r] = X[size_t(r) * n + c];
+    lower_solve(tmp.data());
+    for (int r = 0; r < n; ++r) C[size_t(c) * n + r] = tmp[r];
+  }
+  for (int c = 0; c < n; ++c)
+    for (int r = c + 1; r < n; ++r) {
+      const double v = 0.5 * (C[size_t(c) * n + r] + C[size_t(r) * n + c]);
+      C[size_t(c) * n + r] = v;
+      C[size_t(r) * n + c] = v;
+    }
+  return true;
+}
+
+void fd_exact_vectors(const std::vector<double>& L, int n, int p, double* Q) {
+  for (int c = 0; c < n; ++c) {
+    double* x = Q + size_t(c) * n;
+    for (int i = n - 1; i >= 0; --i) {
+      double s = x[i];
+      for (int k = i + 1; k <= std::min(n - 1, i + p); ++k) s -= L[size_t(k) * (p + 1) + (k - i)] * x[k];
+      x[i] = s / L[size_t(i) * (p + 1)];
+    }
+  }
 }
 
 }  // namespace tk

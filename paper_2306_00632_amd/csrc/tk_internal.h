@@ -77,4 +77,14 @@ struct FdDirection {
 
 bool fd_direction_setup(int n_el, int p, double coef, FdDirection& d, std::string& msg);
 
+// Exact generalized eigenpairs of (coef K, M) on the Dirichlet space, eq.
+// (factorizations): with the banded Cholesky factor M = L L^T (L in the band
+// layout of band_cholesky), C = L^{-1} (coef K) L^{-T} (n x n, column-major,
+// symmetrized) has the same eigenvalues, and U = L^{-T} Q for its orthonormal
+// eigenvectors Q is M-orthonormal.
+bool fd_exact_pencil(int n_el, int p, double coef, std::vector<double>& C, std::vector<double>& L, int& n,
+                     std::string& msg);
+// Q (n x n, column-major) <- L^{-T} Q
+void fd_exact_vectors(const std::vector<double>& L, int n, int p, double* Q);
+
 }  // namespace tk

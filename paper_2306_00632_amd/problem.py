@@ -28,8 +28,8 @@ def rhs(ctx, w) -> tk.Tucker:
     return tk.Tucker.from_host(ctx, core, U)
 
 
-def preconditioner(ctx, w, eps_prec=0.1, coef=(1.0, 1.0, 1.0)) -> tk.Preconditioner:
-    return tk.Preconditioner.create(ctx, w.n_el, w.p, eps_prec, coef)
+def preconditioner(ctx, w, eps_prec=0.1, coef=(1.0, 1.0, 1.0), exact=False) -> tk.Preconditioner:
+    return tk.Preconditioner.create(ctx, w.n_el, w.p, eps_prec, coef, exact=exact)
 
 
 # --- block (3-component) systems --------------------------------------------

@@ -66,6 +66,7 @@ EXPORTS = {
     "tk_op_free": (None, [vp]),
     "tucker_apply_op": (C.c_int32, [vp, vp, vp, C.POINTER(vp)]),
     "fd_setup": (C.c_int32, [vp, i32p, C.c_int32, C.c_double, dp, C.POINTER(vp), i32p]),
+    "fd_setup_exact": (C.c_int32, [vp, i32p, C.c_int32, C.c_double, dp, C.POINTER(vp), i32p]),
     "tk_prec_free": (None, [vp]),
     "tk_prec_info": (C.c_int32, [vp, i32p, dp, dp, dp, dp, dp]),
     "tk_prec_direction": (C.c_int32, [vp, C.c_int32, i32p, i32p, i32p, dp, dp, dp, dp]),
@@ -341,12 +342,15 @@ class Preconditioner(_Handle):
     _free = "tk_prec_free"
 
     @classmethod
-    def create(cls, ctx, n_el, p, eps_prec=0.1, coef=(1.0, 1.0, 1.0)) -> "Preconditioner":
+    def create(cls, ctx, n_el, p, eps_prec=0.1, coef=(1.0, 1.0, 1.0), exact=False) -> "Preconditioner":
+        """Appendix B eigen-approximations (fd_setup), or with exact=True the
+        exact generalized eigenpairs applied as dense GEMMs (fd_setup_exact)."""
         ne = (C.c_int32 * 3)(*((n_el,) * 3 if np.isscalar(n_el) else n_el))
         cf = np.asarray(coef, dtype=np.float64)
         h = vp()
         R = C.c_int32()
-        ctx.check(lib().fd_setup(ctx.h, ne, p, eps_prec, _ptr(cf), C.byref(h), C.byref(R)), "fd_setup")
+        name = "fd_setup_exact" if exact else "fd_setup"
+        ctx.check(getattr(lib(), name)(ctx.h, ne, p, eps_prec, _ptr(cf), C.byref(h), C.byref(R)), name)
         return cls(ctx, h)
 
     def info(self):

@@ -86,12 +86,14 @@ def test_appendix_b_structure(p, n_el):
         # Lambda2 are exact Rayleigh quotients of the V2 U2 columns
         V2U2 = Ut[:, n1:]
         np.testing.assert_allclose(np.diag(V2U2.T @ P["K"] @ V2U2), lam[n1:], rtol=1e-10)
-    # columns of V1 U1 interpolate sqrt(2) sin(j pi x) at the points
+    # columns of V1 U1 interpolate sqrt(2) sin(j pi x) at the points, up to
+    # their normalization to unit L2 (M) norm
     vals = bspline.dirichlet_basis_at(n_el, p, P["x"]) @ Ut[:, :n1]
-    np.testing.assert_allclose(vals, P["Udft"], atol=1e-11)
+    np.testing.assert_allclose(vals / P["scale1"], P["Udft"], atol=1e-11)
+    np.testing.assert_allclose(np.einsum("ij,ij->j", Ut[:, :n1], P["M"] @ Ut[:, :n1]), 1.0, rtol=1e-12)
     np.testing.assert_allclose(lam[:n1], (np.pi * np.arange(1, n1 + 1)) ** 2)
-    # the smooth sines have nearly unit L2 norm (single sqrt(2))
-    assert abs(Ut[:, 0] @ P["M"] @ Ut[:, 0] - 1.0) < 1e-3
+    # the smoothest sine's interpolant already has nearly unit L2 norm
+    assert abs(P["scale1"][0] - 1.0) < 1e-3
 
 
 def test_p2_sines_are_exact_eigenvectors():
@@ -157,14 +159,52 @@ def test_lowrank_fd_apply_matches_dense_inverse(p):
 
 
 def test_lowrank_fd_close_to_exact_fd_spectrally():
-    """P~^{-1} P is well conditioned for p = 2: the eigenvectors are exact
-    there; the interpolated sines are not M-normalised (their squared norms
-    range over about [0.6, 1.07]) and Lambda1 = (j pi)^2 differs from the
-    discrete eigenvalues, which bounds the spectrum away from 0 and infinity."""
-    n_el, p = 6, 2
-    prec = fd.LowRankFD(n_el, p, 0.1)
+    """For p = 2 the normalized interpolated sines are the exact M-orthonormal
+    eigenvectors, so P~^{-1} P is similar to diag(lambda_h s(lambda~)) over the
+    Kronecker sums: each factor lambda_h / lambda~ lies between the extreme
+    1D ratios r_j = lambda_h,j / (j pi)^2 (a ratio of sums lies between the
+    ratios of its terms) and lambda~ s(lambda~) within 1 +- eps_prec (Prop. 1).
+    Unnormalized sines (squared M-norms over about [0.6, 1.07]) fail it."""
+    n_el, p, eps = 6, 2, 0.1
+    prec = fd.LowRankFD(n_el, p, eps)
     K = bspline.matrix(n_el, p, "stiff")
     M = bspline.matrix(n_el, p, "mass")
     Pm = (np.kron(K, np.kron(M, M)) + np.kron(M, np.kron(K, M)) + np.kron(M, np.kron(M, K)))
     ev = np.linalg.eigvals(prec.dense_inverse() @ Pm).real
-    assert ev.min() > 0.2 and ev.max() / ev.min() < 10.0
+    lam_h = np.sort(sla.eigh(K, M, eigvals_only=True))
+    r = lam_h / (np.pi * np.arange(1, len(lam_h) + 1)) ** 2
+    assert ev.min() >= (1 - eps) * r.min() - 1e-9 and ev.max() <= (1 + eps) * r.max() + 1e-9, (ev.min(), ev.max())
+
+
+def test_approximate_and_exact_eigenpairs_similar_iterations():
+    """The remark of Sec. 5: TPCG with exact eigenpairs takes nearly the same
+    number of iterations as with the Appendix B approximations (deformed
+    workload's recipe at n_el = 32; unnormalized sines need twice as many)."""
+    from oracle import problem as oprob, tpcg as otpcg
+    for p in (2, 3):
+        w = W.weighted_cp(32, p, 9, 5, 2002, 2003)
+        op, f = oprob.operator(w), oprob.rhs(w)
+        its = [otpcg.tpcg(op, fd.LowRankFD(32, p, 0.1, exact=ex), f, tol=1e-6, eps_min=1e-8)[1].iters
+               for ex in (False, True)]
+        assert abs(its[0] - its[1]) <= max(2, 0.2 * its[1]), (p, its)
+
+
+@pytest.mark.parametrize("n_el,p", [(5, 2), (6, 3), (7, 4)])
+def test_exact_eigenpair_lowrank_fd_within_prop1_bound(n_el, p):
+    """Algorithm 4 with the exact factorizations (eq. factorizations): P~^{-1} P
+    is similar to diag(lambda s(lambda)) over the Kronecker sums lambda of the
+    1D eigenvalues, and Prop. 1 with R_P from eq. estimate_prec_rel bounds
+    |1 - lambda s(lambda)| by eps_prec on [lambda_min, lambda_max]; the
+    deviation is not zero (the sum approximates 1/lambda, it is not exact).
+    A dropped 1/lambda_min, a wrong exponent or non-M-orthonormal
+    eigenvectors break the bound."""
+    eps = 0.1
+    prec = fd.LowRankFD(n_el, p, eps, exact=True)
+    K = bspline.matrix(n_el, p, "stiff")
+    M = bspline.matrix(n_el, p, "mass")
+    U = prec.Ut[0]
+    np.testing.assert_allclose(U.T @ M @ U, np.eye(U.shape[0]), atol=1e-12)
+    Pm = (np.kron(K, np.kron(M, M)) + np.kron(M, np.kron(K, M)) + np.kron(M, np.kron(M, K)))
+    ev = np.linalg.eigvals(prec.dense_inverse() @ Pm).real
+    assert ev.min() >= 1.0 - eps - 1e-9 and ev.max() <= 1.0 + eps + 1e-9, (ev.min(), ev.max())
+    assert np.abs(ev - 1.0).max() > 1e-3
