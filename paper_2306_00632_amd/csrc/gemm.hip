@@ -262,5 +262,15 @@ void dgemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
   }
 }
 
+// C = sum_z part[z] (+ beta C): the sum of nsplit M x N partial products
+// (part[z] column-major with leading dimension M), e.g. of a batched GEMM
+void splitk_reduce(hipStream_t s, int M, int N, int nsplit, const double* part, double beta, double* C, int ldc) {
+  if (M <= 0 || N <= 0) return;
+  const long long MN = (long long)M * N;
+  const int nb = (int)std::min<long long>(1024, (MN + 255) / 256);
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(nb), dim3(256), 0, s, M, N, nsplit, part, beta, C, ldc);
+  check_launch("splitk_reduce");
+}
+
 }  // namespace gpu
 }  // namespace tk

@@ -20,6 +20,8 @@ void dgemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
            const double* A, int lda, long long sA, const double* B, int ldb, long long sB,
            double beta, double* C, int ldc, long long sC, int batch = 1, double* part = nullptr,
            int nsplit = 1);
+// C = sum_z part[z] (+ beta C) over nsplit M x N partial products (leading dimension M)
+void splitk_reduce(hipStream_t s, int M, int N, int nsplit, const double* part, double beta, double* C, int ldc);
 
 // Householder QR of up to 3 independent tall matrices (m <= n), one
 // workgroup each.  A (n x m, ld n) is overwritten by the reflectors; R (m x m)

@@ -118,6 +118,10 @@ struct tk_ctx {
   tk::BufP scal;  // device scalars: [0] accumulator + 256 scratch, [300..] misc
   tk::BufP sel;   // rank-selection output (ints)
   double* stage = nullptr;  // pinned host staging for scalar readbacks (kStage doubles)
+  // two side streams (default priority) for the speculative ST-HOSVD modes 2
+  // and 3, joined to `stream` by events
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t ev_main = nullptr, ev_side[2] = {nullptr, nullptr};
   // instrumentation (off by default)
   bool prof = false;
   std::vector<tk::ProfRec> recs;
@@ -413,6 +417,21 @@ struct TruncPrep {
   // the first ST-HOSVD mode depends on Z only: its eigenvectors, projection
   // and energies are kept for the retries of Algorithm 2 on the same tensor
   BufP V0, Pm0, part0;
+  // speculative eigenvectors of the Gram matrices of modes 2 and 3 of Z
+  // (computed on the side streams; valid for the sequential ST-HOSVD when the
+  // earlier modes keep every direction, since an orthogonal rotation in one
+  // mode leaves the Gram matrices of the others unchanged)
+  bool spec = false;
+  BufP Vs[2];
+  std::vector<BufP> spec_keep;
+  tk_ctx* spec_ctx = nullptr;  // set once side work is enqueued
+  // on every exit (errors included) the main stream waits for the side work
+  // before the buffers above go back to the pool
+  ~TruncPrep() {
+    if (!spec_ctx) return;
+    for (int i = 0; i < 2; ++i)
+      if (Vs[i]) (void)hipStreamWaitEvent(spec_ctx->stream, spec_ctx->ev_side[i], 0);
+  }
 };
 
 static TruncPrep truncate_prepare(tk_ctx* ctx, const tk_tucker* y) {
@@ -496,6 +515,54 @@ static TruncPrep truncate_prepare(tk_ctx* ctx, const tk_tucker* y) {
 }
 
 // Steps 3-4: ST-HOSVD of Z with tolerance eps, factors Q_k S_k.
+// Modes 2 and 3 of Z on the side streams: G_2 = sum_c Z_c^T Z_c (Z_c the
+// q0 x q1 slices), G_3 = Z^T Z with Z viewed as (q0 q1) x q2, and their
+// eigenvectors.  The side streams start after everything enqueued on the
+// main stream so far (so no pool buffer they receive is still in use there);
+// the main stream waits for them before it uses the results and before the
+// truncation returns (so their buffers go back to the pool in stream order).
+constexpr int kSpecMax = 256;
+static void spec_launch(tk_ctx* ctx, TruncPrep& P) {
+  if (P.spec) return;
+  P.spec = true;
+  const int q0 = P.q[0], q1 = P.q[1], q2 = P.q[2];
+  if (q0 < 2 || q1 < 2 || q2 < 2 || q1 > kSpecMax || q2 > kSpecMax) return;
+  HIPCHK(hipEventRecord(ctx->ev_main, ctx->stream));
+  P.spec_ctx = ctx;
+  const double* Z = P.Z->p;
+  const int a[2] = {q1, q2};
+  for (int i = 0; i < 2; ++i) {
+    hipStream_t s = ctx->side[i];
+    HIPCHK(hipStreamWaitEvent(s, ctx->ev_main, 0));
+    const int n = a[i];
+    BufP G = alloc(ctx, (size_t)n * n), w = alloc(ctx, (size_t)n), work = alloc(ctx, gpu::sym_eig_work(n));
+    P.Vs[i] = alloc(ctx, (size_t)n * n);
+    P.spec_keep.insert(P.spec_keep.end(), {G, w, work});
+    if (i == 0) {
+      BufP part = alloc(ctx, (size_t)q2 * q1 * q1);
+      P.spec_keep.push_back(part);
+      gpu::dgemm(s, true, false, q1, q1, q0, 1.0, Z, q0, (long long)q0 * q1, Z, q0, (long long)q0 * q1, 0.0,
+                 part->p, q1, (long long)q1 * q1, q2);
+      gpu::splitk_reduce(s, q1, q1, q2, part->p, 0.0, G->p, q1);
+    } else {
+      const int K = q0 * q1;
+      const int ns = gpu::dgemm_split_count(q2, q2, K);
+      BufP part;
+      if (ns > 1) {
+        part = alloc(ctx, (size_t)ns * q2 * q2);
+        P.spec_keep.push_back(part);
+      }
+      gpu::dgemm(s, true, false, q2, q2, K, 1.0, Z, K, 0, Z, K, 0, 0.0, G->p, q2, 0, 1, part ? part->p : nullptr, ns);
+    }
+    gpu::sym_eig(s, G->p, n, P.Vs[i]->p, w->p, work->p);
+    HIPCHK(hipEventRecord(ctx->ev_side[i], s));
+  }
+}
+
+static void spec_join(tk_ctx* ctx, const TruncPrep& P, int i) {
+  if (P.Vs[i]) HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_side[i], 0));
+}
+
 static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double* disc_rel) {
   int dims[3] = {P.q[0], P.q[1], P.q[2]};
   BufP cur = P.Z;
@@ -510,10 +577,23 @@ static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double*
     const int a = dims[0], bc = dims[1] * dims[2];
     const int nseg = gpu::column_energy_parts(bc);
     BufP V, Pm, part;
+    if (k == 0) spec_launch(ctx, P);
+    // the speculative eigenvectors hold when every earlier mode kept all its directions
+    const bool use_spec = k > 0 && P.Vs[k - 1] && s_k[0] == P.q[0] && (k == 1 || s_k[1] == P.q[1]);
     if (k == 0 && P.V0) {
       V = P.V0;
       Pm = P.Pm0;
       part = P.part0;
+    } else if (use_spec) {
+      spec_join(ctx, P, k - 1);
+      V = P.Vs[k - 1];
+      Pm = alloc(ctx, (size_t)bc * a);
+      gemm(ctx, true, false, bc, a, a, 1.0, cur->p, a, V->p, a, 0.0, Pm->p, bc);
+      part = alloc(ctx, (size_t)a * nseg);
+      {
+        Prof pr(ctx, PK_SELECT, 8.0 * bc * (double)a, 2.0 * bc * (double)a);
+        gpu::column_energy(ctx->stream, Pm->p, bc, a, part->p);
+      }
     } else {
       // Gram of the mode-k unfolding (the current leading mode)
       BufP G = alloc(ctx, (size_t)a * a);
@@ -568,6 +648,9 @@ static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double*
     dims[1] = dims[2];
     dims[2] = s;
   }
+  // the side streams' buffers may return to the pool only after the main stream has waited for them
+  spec_join(ctx, P, 0);
+  spec_join(ctx, P, 1);
   if (disc_rel) *disc_rel = (P.norm2 > 0) ? disc_total / P.norm2 : 0.0;
   int n[3] = {P.n[0], P.n[1], P.n[2]};
   if (zero) {
@@ -1029,6 +1112,11 @@ tk_status tk_ctx_create(int device, void* hip_stream, tk_ctx** out) {
     c->scal = alloc(c, 512);
     c->sel = alloc(c, 1100);  // 2200 ints
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&c->stage), kStage * sizeof(double), hipHostMallocDefault));
+    for (int i = 0; i < 2; ++i) {
+      HIPCHK(hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&c->ev_side[i], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming));
     return TK_OK;
   });
   if (st != TK_OK) {
@@ -1043,6 +1131,14 @@ void tk_ctx_destroy(tk_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  for (int i = 0; i < 2; ++i) {
+    if (ctx->side[i]) {
+      (void)hipStreamSynchronize(ctx->side[i]);
+      (void)hipStreamDestroy(ctx->side[i]);
+    }
+    if (ctx->ev_side[i]) (void)hipEventDestroy(ctx->ev_side[i]);
+  }
+  if (ctx->ev_main) (void)hipEventDestroy(ctx->ev_main);
   for (auto& r : ctx->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
