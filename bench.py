@@ -24,10 +24,16 @@ Prints one JSON line (see the "metric" key) with:
                        HBM bytes of the big launch from the committed
                        FETCH_SIZE / WRITE_SIZE summary (null once the kernel
                        source has changed since it was taken)
+  serving              a seeded mix of solves served with several concurrent
+                       solves (one stream and library context each) against
+                       the plain one-at-a-time path: solves/s and p50/p99
+                       latency at Poisson arrival rates of 0.5, 1 and 2 times
+                       the plain capacity and with all requests at once
   cpu_baseline         the FP64 oracle on the host cores (bounded sample)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload deformed|small]
-                       [--fd approx|exact] [--no-hbm] [--no-cpu-baseline]
+                       [--fd approx|exact] [--no-hbm] [--no-serve] [--serve-slots S]
+                       [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -179,6 +185,39 @@ def mode_products_hbm(ctx, reps=5):
     return out
 
 
+# eps_min 1e-9: the paper's remedy for the stagnation of Sec. 5.3 (one request of
+# this mix stalls near 1.4e-6 with 1e-8); maxit 300 bounds a stalled request
+SERVE_MIX = dict(count=24, seed=4000, n_els=(64, 128), ps=(2, 3, 4), Rs=(3, 6, 9), ranks=range(1, 11),
+                 eps_min=1e-9, maxit=300)
+
+
+def serving(slots=8):
+    """Continuous serving of a seeded mix of solves (the deformed recipe at
+    n_el in {64, 128}, p in {2, 3, 4}, 3/6/9 terms, rhs rank 1..10): the plain
+    path (one slot, one solve at a time) gives the capacity mu_plain; the
+    server with `slots` concurrent solves then runs the same requests with
+    Poisson arrivals at 0.5, 1 and 2 mu_plain and with all of them at once.
+    Latency = completion - arrival (queueing and per-request setup included)."""
+    from paper_2306_00632_amd import serve
+    reqs = serve.mixed_requests(**SERVE_MIX)
+    plain_srv = serve.Server(slots=1)
+    plain_srv.run(reqs[:2])  # warm-up (code objects, pools)
+    plain = serve.summarize(plain_srv.run(reqs))
+    plain_srv.close()
+    mu = plain["solves_per_s"]
+    out = {"requests": len(reqs),
+           "mix": {k: list(v) if isinstance(v, (tuple, range)) else v for k, v in SERVE_MIX.items()},
+           "slots": slots, "plain": plain, "served": {}}
+    srv = serve.Server(slots=slots)
+    srv.run(reqs[:slots])  # warm-up of every slot
+    for name, rate in (("0.5x", 0.5 * mu), ("1x", mu), ("2x", 2.0 * mu), ("all_at_once", 0.0)):
+        res = srv.run(serve.poisson_arrivals(reqs, rate, SERVE_MIX["seed"] + 7))
+        out["served"][name] = dict(serve.summarize(res), arrival_rate=rate)
+    srv.close()
+    out["speedup_all_at_once"] = out["served"]["all_at_once"]["solves_per_s"] / mu
+    return out
+
+
 def cpu_baseline(w, gpu_iters, target_s=12.0, exact=False):
     """The oracle's TPCG (unchanged) on a bounded sample of the same solve:
     the first k TPCG iterations (including the initial preconditioner and
@@ -218,6 +257,8 @@ def main():
     ap.add_argument("--workload", default="deformed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm", action="store_true", help="skip the batched mode-product bandwidth runs")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--fd", choices=("approx", "exact"), default="approx",
                     help="preconditioner eigenpairs: Appendix B approximations applied by sine transforms "
                          "(default) or the exact generalized eigenpairs applied by dense GEMMs")
@@ -331,6 +372,8 @@ def main():
     }
     if not args.no_hbm:
         out["mode_products_hbm"] = mode_products_hbm(ctx)
+    if not args.no_serve:
+        out["serving"] = serving(args.serve_slots)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline(w, last_info["iters"], exact=(args.fd == "exact"))
     print(json.dumps(out), flush=True)
