@@ -41,6 +41,13 @@ import os
 import sys
 import time
 
+# HIP maps every stream of the process onto this many hardware queues (4 by
+# default); a solve uses three streams (the main one and two for the
+# speculative ST-HOSVD modes) and the serving runs one solve per slot, so
+# with 4 queues independent kernels serialise behind each other.  Read by
+# the HIP runtime at initialisation, so it is set before torch is imported.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -187,11 +194,11 @@ def mode_products_hbm(ctx, reps=5):
 
 # eps_min 1e-9: the paper's remedy for the stagnation of Sec. 5.3 (one request of
 # this mix stalls near 1.4e-6 with 1e-8); maxit 300 bounds a stalled request
-SERVE_MIX = dict(count=24, seed=4000, n_els=(64, 128), ps=(2, 3, 4), Rs=(3, 6, 9), ranks=range(1, 11),
+SERVE_MIX = dict(count=48, seed=4000, n_els=(64, 128), ps=(2, 3, 4), Rs=(3, 6, 9), ranks=range(1, 11),
                  eps_min=1e-9, maxit=300)
 
 
-def serving(slots=8):
+def serving(slots=16):
     """Continuous serving of a seeded mix of solves (the deformed recipe at
     n_el in {64, 128}, p in {2, 3, 4}, 3/6/9 terms, rhs rank 1..10): the plain
     path (one slot, one solve at a time) gives the capacity mu_plain; the
@@ -258,7 +265,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm", action="store_true", help="skip the batched mode-product bandwidth runs")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--fd", choices=("approx", "exact"), default="approx",
                     help="preconditioner eigenpairs: Appendix B approximations applied by sine transforms "
                          "(default) or the exact generalized eigenpairs applied by dense GEMMs")

@@ -11,6 +11,12 @@ the HBM budget.  A request builds its operator, preconditioner and
 right-hand side in its slot's context, solves, copies the solution's
 Tucker data to the host if asked, and releases its device memory.
 
+HIP multiplexes the streams of a process onto GPU_MAX_HW_QUEUES hardware
+queues (4 by default); each slot drives three streams (its solve's main
+stream and two for the speculative ST-HOSVD modes), so set the variable to
+16 or so before HIP initialises, or independent kernels of different slots
+serialise in a shared queue (bench.py does).
+
 Latency of a request = completion - arrival (queueing included); throughput
 = completions / makespan.  Every kernel of the library is deterministic, so
 a request's result does not depend on what else is in flight.
