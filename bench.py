@@ -24,6 +24,9 @@ Prints one JSON line (see the "metric" key) with:
                        HBM bytes of the big launch from the committed
                        FETCH_SIZE / WRITE_SIZE summary (null once the kernel
                        source has changed since it was taken)
+  matrix_cores         the library's DGEMM at order 4096 (probe of the FP64
+                       matrix-core rate it reaches) and the solve's GEMMs as
+                       fractions of the 78.6 TFLOP/s spec and of that probe
   serving              a seeded mix of solves served with several concurrent
                        solves (one stream and library context each) against
                        the plain one-at-a-time path: solves/s and p50/p99
@@ -192,6 +195,39 @@ def mode_products_hbm(ctx, reps=5):
     return out
 
 
+def matrix_cores(ctx, solve_kernels, reps=5):
+    """FP64 matrix-core rates: a square GEMM of order 4096 through the
+    library's own DGEMM (tk_dgemm, the kernel of every dense contraction of
+    the truncation) as the probe of what the kernel reaches on this GPU, and
+    the solve's GEMMs (algorithmic 2MNK flops over their kernel time, from the
+    instrumented solve) as fractions of the spec peak and of that probe."""
+    import torch
+    from paper_2306_00632_amd import tk
+    n = 4096
+    g = torch.Generator(device="cuda").manual_seed(5)
+    A = torch.randn(n * n, dtype=torch.float64, device="cuda", generator=g)
+    B = torch.randn(n * n, dtype=torch.float64, device="cuda", generator=g)
+    C = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+    tk.dgemm(ctx, False, False, n, n, n, 1.0, A, n, B, n, 0.0, C, n)   # warm-up
+    ctx.sync()
+    ctx.prof(True)
+    for _ in range(reps):
+        tk.dgemm(ctx, False, False, n, n, n, 1.0, A, n, B, n, 0.0, C, n)
+    ctx.sync()
+    k = ctx.prof_read()["dgemm"]
+    ctx.prof(False)
+    del A, B, C
+    probe = k["flops"] / (k["ms"] / 1e3) / 1e12
+    out = {"probe": {"call": "tk_dgemm", "M": n, "N": n, "K": n, "ms_per_call": k["ms"] / reps,
+                     "TFLOP_s": probe, "frac": probe / PEAK_FP64_TFLOPS}}
+    d = solve_kernels.get("dgemm")
+    if d and d["ms_per_solve"] > 0:
+        tf = d["GFLOP_s"] / 1e3
+        out["solve_dgemm"] = {"launches_per_solve": d["launches_per_solve"], "ms_per_solve": d["ms_per_solve"],
+                              "TFLOP_s": tf, "frac": tf / PEAK_FP64_TFLOPS, "frac_of_probe": tf / probe}
+    return out
+
+
 # eps_min 1e-9: the paper's remedy for the stagnation of Sec. 5.3 (one request of
 # this mix stalls near 1.4e-6 with 1e-8); maxit 300 bounds a stalled request
 SERVE_MIX = dict(count=48, seed=4000, n_els=(64, 128), ps=(2, 3, 4), Rs=(3, 6, 9), ranks=range(1, 11),
@@ -263,7 +299,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="deformed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-hbm", action="store_true", help="skip the batched mode-product bandwidth runs")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the batched mode-product bandwidth runs and the DGEMM probe")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--fd", choices=("approx", "exact"), default="approx",
@@ -379,6 +415,7 @@ def main():
     }
     if not args.no_hbm:
         out["mode_products_hbm"] = mode_products_hbm(ctx)
+        out["matrix_cores"] = matrix_cores(ctx, kernels)
     if not args.no_serve:
         out["serving"] = serving(args.serve_slots)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
