@@ -23,7 +23,9 @@ Prints one JSON line (see the "metric" key) with:
                        plain device copy measured in the same run, and the
                        HBM bytes of the big launch from the committed
                        FETCH_SIZE / WRITE_SIZE summary (null once the kernel
-                       source has changed since it was taken)
+                       source has changed since it was taken); the same runs
+                       with FP32 arithmetic (band_apply_f32, fd_chain_f32:
+                       FP64 data, bytes counted alike)
   matrix_cores         the library's DGEMM at order 4096 (probe of the FP64
                        matrix-core rate it reaches) and the solve's GEMMs as
                        fractions of the 78.6 TFLOP/s spec and of that probe
@@ -35,8 +37,8 @@ Prints one JSON line (see the "metric" key) with:
   cpu_baseline         the FP64 oracle on the host cores (bounded sample)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload deformed|small]
-                       [--fd approx|exact] [--no-hbm] [--no-serve] [--serve-slots S]
-                       [--no-cpu-baseline]
+                       [--fd approx|exact] [--arith f64|mixed] [--no-hbm] [--no-serve]
+                       [--serve-slots S] [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -145,24 +147,29 @@ def mode_products_hbm(ctx, reps=5):
     op = problem.operator(ctx, w)
     x = tk.Tucker.from_host(ctx, core, U)
     del U
-    y = tk.tucker_apply_op(ctx, op, x)   # warm-up
-    del y
-    ctx.sync()
-    ctx.prof(True)
-    for _ in range(reps):
-        y = tk.tucker_apply_op(ctx, op, x)
+
+    def band(arith):
+        y = tk.tucker_apply_op(ctx, op, x, arith=arith)   # warm-up
         del y
-    ctx.sync()
-    k = ctx.prof_read()["band_apply"]
-    ctx.prof(False)
-    del x, op
-    gbs = k["bytes"] / (k["ms"] / 1e3) / 1e9
+        ctx.sync()
+        ctx.prof(True)
+        for _ in range(reps):
+            y = tk.tucker_apply_op(ctx, op, x, arith=arith)
+            del y
+        ctx.sync()
+        k = ctx.prof_read()["band_apply"]
+        ctx.prof(False)
+        gbs = k["bytes"] / (k["ms"] / 1e3) / 1e9
+        return {"call": "tucker_apply_op" if arith == "f64" else "tucker_apply_op_arith", "arith": arith,
+                "n_el": w.n_el, "p": w.p, "n": w.n, "R": len(w.nnz), "ranks": [K1_SHAPE["m"], 1, 1],
+                "GB_per_call": k["bytes"] / reps / 1e9, "ms_per_call": k["ms"] / reps, "GB_s": gbs,
+                "frac": gbs / PEAK_HBM_GBS, "frac_of_copy": gbs / copy_gbs}
+
     tr = measured_traffic("band_apply_batched")
-    out["band_apply"] = {"call": "tucker_apply_op", "n_el": w.n_el, "p": w.p, "n": w.n, "R": len(w.nnz),
-                         "ranks": [K1_SHAPE["m"], 1, 1], "GB_per_call": k["bytes"] / reps / 1e9,
-                         "ms_per_call": k["ms"] / reps, "GB_s": gbs, "frac": gbs / PEAK_HBM_GBS,
-                         "frac_of_copy": gbs / copy_gbs,
-                         "traffic_GB_big_launch": None if tr is None else tr / 1e9}
+    out["band_apply"] = band("f64")
+    out["band_apply"]["traffic_GB_big_launch"] = None if tr is None else tr / 1e9
+    out["band_apply_f32"] = band("f32")
+    del x, op
     core, U = k2_inputs()
     P = tk.Preconditioner.create(ctx, K2_SHAPE["n_el"], K2_SHAPE["p"], 0.1)
     info = P.info()
@@ -170,28 +177,34 @@ def mode_products_hbm(ctx, reps=5):
     s = tk.Tucker.from_host(ctx, core, U)
     n = U[0].shape[0]
     del U
-    z = tk.fd_precond(ctx, P, s)   # warm-up
-    del z
-    ctx.sync()
-    ctx.prof(True)
-    for _ in range(reps):
-        z = tk.fd_precond(ctx, P, s)
-        del z
-    ctx.sync()
-    kk = ctx.prof_read()
-    ctx.prof(False)
-    del s, P
     Rp = info["R_P"]
     cols = K2_SHAPE["m"] + 2
     by = 8.0 * ((1 + Rp) * n * cols + 3 * n * n2)
-    ms = kk["fd_forward"]["ms"] + kk["fd_backward"]["ms"]
-    gbs = by * reps / (ms / 1e3) / 1e9
-    out["fd_chain"] = {"call": "fd_precond", "n_el": K2_SHAPE["n_el"], "p": K2_SHAPE["p"], "n": n, "R_P": Rp,
-                       "ranks": [K2_SHAPE["m"], 1, 1], "GB_per_call": by / 1e9, "ms_per_call": ms / reps,
-                       "ms_forward": kk["fd_forward"]["ms"] / reps, "ms_backward": kk["fd_backward"]["ms"] / reps,
-                       "GB_s": gbs, "frac": gbs / PEAK_HBM_GBS, "frac_of_copy": gbs / copy_gbs}
+
+    def fd(arith):
+        z = tk.fd_precond(ctx, P, s, arith=arith)   # warm-up
+        del z
+        ctx.sync()
+        ctx.prof(True)
+        for _ in range(reps):
+            z = tk.fd_precond(ctx, P, s, arith=arith)
+            del z
+        ctx.sync()
+        kk = ctx.prof_read()
+        ctx.prof(False)
+        ms = kk["fd_forward"]["ms"] + kk["fd_backward"]["ms"]
+        gbs = by * reps / (ms / 1e3) / 1e9
+        return {"call": "fd_precond" if arith == "f64" else "fd_precond_arith", "arith": arith,
+                "n_el": K2_SHAPE["n_el"], "p": K2_SHAPE["p"], "n": n, "R_P": Rp, "ranks": [K2_SHAPE["m"], 1, 1],
+                "GB_per_call": by / 1e9, "ms_per_call": ms / reps, "ms_forward": kk["fd_forward"]["ms"] / reps,
+                "ms_backward": kk["fd_backward"]["ms"] / reps, "GB_s": gbs, "frac": gbs / PEAK_HBM_GBS,
+                "frac_of_copy": gbs / copy_gbs}
+
+    out["fd_chain"] = fd("f64")
     tf, tb = measured_traffic("fd_forward_batched"), measured_traffic("fd_backward_batched")
     out["fd_chain"]["traffic_GB_big_launches"] = None if tf is None or tb is None else (tf + tb) / 1e9
+    out["fd_chain_f32"] = fd("f32")
+    del s, P
     return out
 
 
@@ -305,6 +318,9 @@ def main():
     ap.add_argument("--fd", choices=("approx", "exact"), default="approx",
                     help="preconditioner eigenpairs: Appendix B approximations applied by sine transforms "
                          "(default) or the exact generalized eigenpairs applied by dense GEMMs")
+    ap.add_argument("--arith", choices=("f64", "mixed"), default="f64",
+                    help="f64: every step in FP64; mixed: the preconditioner and the direction's operator "
+                         "products in FP32 arithmetic where the precision rule allows (TK_ARITH_MIXED)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of MIB MiB (read + write) before the solves, "
                          "as the known-size reference of a rocprofv3 FETCH_SIZE/WRITE_SIZE run")
@@ -332,7 +348,7 @@ def main():
     op = problem.operator(ctx, w)
     prec = problem.preconditioner(ctx, w, exact=(args.fd == "exact"))
     f = problem.rhs(ctx, w)
-    params = dict(tol=w.tol, eps_min=w.eps_min)
+    params = dict(tol=w.tol, eps_min=w.eps_min, arith=args.arith)
     for _ in range(args.warmup):
         x, info = tk.tpcg_solve(ctx, op, prec, f, **params)
         del x
@@ -400,9 +416,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.arith == "f64" else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "fd_eigenpairs": args.fd, "n_el": w.n_el, "p": w.p, "dofs_per_direction": w.n,
+        "config": {"workload": w.name, "fd_eigenpairs": args.fd, "arith": args.arith,
+                   "f32_applications": last_info["f32_applications"], "n_el": w.n_el, "p": w.p,
+                   "dofs_per_direction": w.n,
                    "kronecker_terms": len(w.nnz), "rhs_rank": int(np.asarray(problem.rhs_arrays(w)[0]).shape[0]),
                    "tol": w.tol, "iters": last_info["iters"], "relres": last_info["relres"],
                    "solution_rank": list(last_info["rank"]), "trel_calls": last_info["trel_calls"]},

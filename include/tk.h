@@ -150,6 +150,18 @@ void tk_op_free(tk_op* op);
  * as one block per nonzero of C.  Asynchronous. */
 tk_status tucker_apply_op(tk_ctx* ctx, const tk_op* op, const tk_tucker* x, tk_tucker** y);
 
+/* Arithmetic of the mode products (the factors stay FP64 in memory). */
+enum { TK_ARITH_F64 = 0, TK_ARITH_F32 = 1 };
+
+/* tucker_apply_op with the arithmetic chosen: TK_ARITH_F32 rounds the bands
+ * (an FP32 copy made by tk_op_create) and the staged factor rows to FP32,
+ * accumulates in FP32 and widens the sums to FP64 on the store (relative
+ * error of order (2p+1) 2^-24 per entry); TK_ARITH_F64 is tucker_apply_op.
+ * The FP32 arithmetic of the growth direction on precision of the mode
+ * products (eq. tt_product).  EINVAL on another value.  Asynchronous. */
+tk_status tucker_apply_op_arith(tk_ctx* ctx, const tk_op* op, const tk_tucker* x, int32_t arith,
+                                tk_tucker** y);
+
 /* ---- low-rank FD preconditioner (Algorithm 4, Appendix B) ----------------- */
 
 /* Setup from the parametric 1D stiffness and mass (Dirichlet at both ends)
@@ -186,6 +198,15 @@ tk_status tk_prec_info(const tk_prec* P, int32_t* R_P, double* lam_min, double* 
  * eigenvector matrix); from fd_setup_exact by GEMMs with the dense exact U.
  * Asynchronous. */
 tk_status fd_precond(tk_ctx* ctx, const tk_prec* P, const tk_tucker* s, tk_tucker** v);
+
+/* fd_precond with the arithmetic chosen (Algorithm 4, steps 5-9):
+ * TK_ARITH_F32 runs the boundary maps, sine transforms, exponential scalings
+ * and V_2 products in FP32 with tables rounded at fd_setup, reading and
+ * writing FP64 factors (relative error of order log2(n) 2^-24 per factor
+ * entry); TK_ARITH_F64 is fd_precond.  A preconditioner from fd_setup_exact
+ * runs in FP64 either way.  EINVAL on another value.  Asynchronous. */
+tk_status fd_precond_arith(tk_ctx* ctx, const tk_prec* P, const tk_tucker* s, int32_t arith,
+                           tk_tucker** v);
 
 /* Appendix B data of direction k for inspection (host, caller-owned):
  * lam (n), g (n1), E (n x n1 dense, column-major), v2u2 (n x n2). Any may be NULL.
@@ -239,7 +260,16 @@ typedef struct {
   double delta;    /* update-ratio threshold of Algorithm 2 (1e-3) */
   int32_t maxit;   /* iteration cap (1000) */
   int32_t verbose; /* 1: print one line per iteration to stderr */
+  int32_t arith;   /* TK_ARITH_F64 (default) or TK_ARITH_MIXED: the preconditioner
+                      application z = P(r) and the operator application q = A p
+                      run in FP32 arithmetic whenever the relative tolerance
+                      eta_k of the truncation that follows is >= 10 * 2^-24;
+                      the x update, the residual f - A x, scalar products and
+                      truncations stay FP64 (the residual is recomputed from x,
+                      so the FP32 steps change the search directions only) */
 } tk_tpcg_params;
+
+enum { TK_ARITH_MIXED = 2 };
 
 typedef struct {
   int32_t iters;
@@ -248,6 +278,7 @@ typedef struct {
   int64_t rank[3];       /* multilinear rank of the solution */
   double eps_final;      /* last dynamic-truncation tolerance */
   int32_t trel_calls;    /* number of relative truncations performed */
+  int32_t f32_applications; /* preconditioner and operator applications run in FP32 */
 } tk_tpcg_info;
 
 /* ---- instrumentation ----------------------------------------------------- */

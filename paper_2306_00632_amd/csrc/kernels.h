@@ -7,8 +7,9 @@
 namespace tk {
 namespace gpu {
 
-// W[:, t*m + c] = A_t Y[:, c] for the nmat banded matrices (DIA, half-bandwidth p)
-void band_apply(hipStream_t s, int n, int m, int nmat, int p, const double* band,
+// W[:, t*m + c] = A_t Y[:, c] for the nmat banded matrices (DIA, half-bandwidth p);
+// Y and W FP64, the arithmetic FP32 with the bands band_f when band_f is given
+void band_apply(hipStream_t s, int n, int m, int nmat, int p, const double* band, const float* band_f,
                 const double* Y, int ldy, double* W, int ldw);
 
 // C = alpha op(A) op(B) + beta C, batched with element strides.  With
@@ -82,27 +83,35 @@ void fill(hipStream_t s, double* x, long long n, double v);
 void scale_copy(hipStream_t s, const double* x, long long n, double a, double* y);
 
 // Low-rank FD transform of one direction (see setup_fd.cpp).
+// the transform's real tables in one arithmetic type (complex ones as
+// interleaved (re, im) pairs)
+template <class T>
+struct FdTab {
+  const T* g = nullptr;       // n1
+  const T* e_val = nullptr;   // n * ke
+  const T* et_val = nullptr;  // n1 * ket
+  const T* v2u2 = nullptr;    // n x n2
+  const T* ge = nullptr;      // R x n: exp(-alpha_j lam_m / lam_min), times g_m for m < n1
+  const T* cs = nullptr;      // N complex: exp(-2 pi i x / N)
+  const T* sn = nullptr;      // N: sin(pi x / N)
+  const T* tq = nullptr;      // N/2 + 1 complex: exp(-i pi x / (2N))
+};
 struct FdDev {
   int n, n1, n2, N, odd, ke, ket, R;
   // rows [e_lo, e_hi) of E hold a single 1 at column row + e_sh; rows
   // [et_lo, et_hi) of E^T a single 1 at column row + et_sh; the others use
   // the ELL tables
   int e_lo, e_hi, e_sh, et_lo, et_hi, et_sh;
-  const double* g;       // n1
   const int* e_idx;      // n * ke
-  const double* e_val;
   const int* et_idx;     // n1 * ket
-  const double* et_val;
-  const double* v2u2;    // n x n2
-  const double* ge;      // R x n: exp(-alpha_j lam_m / lam_min), times g_m for m < n1
-  const double2* cs;     // N: exp(-2 pi i x / N)
-  const double* sn;      // N: sin(pi x / N)
-  const double2* tq;     // N/2 + 1: exp(-i pi x / (2N))
+  FdTab<double> t64;     // FP64 arithmetic
+  FdTab<float> t32;      // FP32 arithmetic (the same values rounded)
 };
-// Z (n x r) = U~^T S (n x r, ld lds)
-void fd_forward(hipStream_t s, const FdDev& d, const double* S, int lds, int r, double* Z);
-// Y[:, j*r + c] = U~ D_j Z[:, c] for j < R, c < r  (Y ld = n)
-void fd_backward(hipStream_t s, const FdDev& d, const double* Z, int r, double* Y);
+// Z (n x r) = U~^T S (n x r, ld lds); S and Z FP64, the arithmetic FP32 when f32
+void fd_forward(hipStream_t s, const FdDev& d, const double* S, int lds, int r, double* Z, bool f32);
+// Y[:, j*r + c] = U~ D_j Z[:, c] for j < R, c < r  (Y ld = n); FP64 data,
+// the arithmetic FP32 when f32
+void fd_backward(hipStream_t s, const FdDev& d, const double* Z, int r, double* Y, bool f32);
 // exact-eigenvector variant: W[:, j r + c] = E[j, :] .* Z[:, c] (E: R x n, row j
 // at E + j n; Z: n x r; W: n x R r)
 void fd_exact_scale(hipStream_t s, int n, int r, int R, const double* E, const double* Z, double* W);

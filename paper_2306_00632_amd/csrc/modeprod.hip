@@ -36,13 +36,15 @@ constexpr int kBandCols = 8;     // factor columns per workgroup (band rows reus
 // rows of Y in LDS; each thread keeps the 2p + 1 band entries of its row of
 // A_t in registers, loading those of A_{t+1} while it applies A_t to every
 // staged column.  All loads are unconditional (clamped indices), only
-// stores are guarded, so the loads of a step issue together.
-template <int PD>
-__global__ __launch_bounds__(kBandRows) void k_band_apply(int n, int m, int nmat, const double* __restrict__ band,
+// stores are guarded, so the loads of a step issue together.  Y and W are
+// FP64; T is the arithmetic type (the bands are stored in T, the staged
+// window is rounded to T, the sums are widened on the store).
+template <int PD, class T>
+__global__ __launch_bounds__(kBandRows) void k_band_apply(int n, int m, int nmat, const T* __restrict__ band,
                                                           const double* __restrict__ Y, int ldy,
                                                           double* __restrict__ W, int ldw) {
   constexpr int NB = 2 * PD + 1, WIN = kBandRows + 2 * PD;
-  __shared__ double ys[kBandCols * WIN];
+  __shared__ T ys[kBandCols * WIN];
   const int i0 = blockIdx.x * kBandRows;
   const int c0 = blockIdx.y * kBandCols;
   const int nc = min(kBandCols, m - c0);
@@ -53,46 +55,55 @@ __global__ __launch_bounds__(kBandRows) void k_band_apply(int n, int m, int nmat
     for (int h = 0; h < 2; ++h) {
       const int t = min((int)threadIdx.x + h * kBandRows, WIN - 1);
       const int i = i0 - PD + t;
-      const double v = col[min(max(i, 0), n - 1)];
-      ys[cc * WIN + t] = (i >= 0 && i < n) ? v : 0.0;
+      const T v = T(col[min(max(i, 0), n - 1)]);
+      ys[cc * WIN + t] = (i >= 0 && i < n) ? v : T(0);
     }
   }
   __syncthreads();
   const int i = i0 + threadIdx.x;
   if (i >= n) return;
-  double bv[NB], bnext[NB];
+  T bv[NB], bnext[NB];
 #pragma unroll
   for (int o = 0; o < NB; ++o) bv[o] = band[(long long)o * n + i];
   for (int t = 0; t < nmat; ++t) {
-    const double* bt = band + (long long)min(t + 1, nmat - 1) * NB * n + i;
+    const T* bt = band + (long long)min(t + 1, nmat - 1) * NB * n + i;
 #pragma unroll
     for (int o = 0; o < NB; ++o) bnext[o] = bt[(long long)o * n];
 #pragma unroll
     for (int cc = 0; cc < kBandCols; ++cc) {
-      const double* yw = ys + cc * WIN + threadIdx.x;
-      double acc = 0.0;
+      const T* yw = ys + cc * WIN + threadIdx.x;
+      T acc = T(0);
 #pragma unroll
       for (int o = 0; o < NB; ++o) acc += bv[o] * yw[o];
       // streaming store: the R outputs are written once and read by later kernels
-      if (cc < nc) __builtin_nontemporal_store(acc, W + i + (long long)(t * m + c0 + cc) * ldw);
+      if (cc < nc) __builtin_nontemporal_store(double(acc), W + i + (long long)(t * m + c0 + cc) * ldw);
     }
 #pragma unroll
     for (int o = 0; o < NB; ++o) bv[o] = bnext[o];
   }
 }
 
-void band_apply(hipStream_t s, int n, int m, int nmat, int p, const double* band,
-                const double* Y, int ldy, double* W, int ldw) {
-  if (n <= 0 || m <= 0 || nmat <= 0) return;
+template <class T>
+static void band_apply_t(hipStream_t s, int n, int m, int nmat, int p, const T* band, const double* Y, int ldy,
+                         double* W, int ldw) {
   dim3 grid((n + kBandRows - 1) / kBandRows, (m + kBandCols - 1) / kBandCols);
   if (grid.y > 65535) throw std::runtime_error("band_apply: more than 524280 columns");
   switch (p) {
 #define TK_BAND(PD) \
-  case PD: hipLaunchKernelGGL(k_band_apply<PD>, grid, dim3(kBandRows), 0, s, n, m, nmat, band, Y, ldy, W, ldw); break;
+  case PD: hipLaunchKernelGGL((k_band_apply<PD, T>), grid, dim3(kBandRows), 0, s, n, m, nmat, band, Y, ldy, W, ldw); break;
     TK_BAND(0) TK_BAND(1) TK_BAND(2) TK_BAND(3) TK_BAND(4) TK_BAND(5) TK_BAND(6)
 #undef TK_BAND
     default: throw std::runtime_error("band_apply: half-bandwidth above 6");
   }
+}
+
+void band_apply(hipStream_t s, int n, int m, int nmat, int p, const double* band, const float* band_f,
+                const double* Y, int ldy, double* W, int ldw) {
+  if (n <= 0 || m <= 0 || nmat <= 0) return;
+  if (band_f)
+    band_apply_t<float>(s, n, m, nmat, p, band_f, Y, ldy, W, ldw);
+  else
+    band_apply_t<double>(s, n, m, nmat, p, band, Y, ldy, W, ldw);
   check_launch("band_apply");
 }
 
@@ -155,11 +166,38 @@ __device__ __forceinline__ int xcd_order(int b, int G) {
 constexpr int kFdWave = 64;
 constexpr int kFdMaxV2 = 4;  // V_2 columns: p - 1 or p - 2, at most 4 for p <= 6
 
+// Single-precision loads for the float tables (same range rule as above).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const float* p, long long count) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, (int)(unsigned)(count * 4), kBufWord3);
+}
+template <class T>
+__device__ __forceinline__ T buf_ldt(__amdgpu_buffer_rsrc_t r, int i, bool ok) {
+  if constexpr (sizeof(T) == 8)
+    return buf_ld(r, i, ok);
+  else
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, ok ? unsigned(i) * 4u : kBufOff, 0, 0));
+}
+
+// The transform's tables in the arithmetic type T of the kernel
+template <class T>
+__device__ __forceinline__ const FdTab<T>& fd_tab(const FdDev& d) {
+  if constexpr (sizeof(T) == 8)
+    return d.t64;
+  else
+    return d.t32;
+}
+
 template <int M>
 struct FdShape {
   static constexpr int RL = M < 8 ? M : 8;
   static constexpr int P = M / RL;
   static constexpr int B = kFdWave / P;
+};
+
+// complex value of the arithmetic type (16-byte aligned for double, 8 for float)
+template <class T>
+struct alignas(2 * sizeof(T)) Cx {
+  T x, y;
 };
 
 // LDS views of a slot, padded against bank conflicts (lanes that touch 8
@@ -169,51 +207,58 @@ template <int M>
 struct FdSlot {
   static constexpr int SIZE = M + M / 8;  // complex elements
 };
+template <class T>
 struct CBuf {
-  double2* p;
-  __device__ __forceinline__ double2& operator[](int i) const { return p[i + (i >> 3)]; }
+  Cx<T>* p;
+  __device__ __forceinline__ Cx<T>& operator[](int i) const { return p[i + (i >> 3)]; }
 };
+template <class T>
 struct RBuf {
-  double* p;
-  __device__ __forceinline__ double& operator[](int i) const { return p[i + (i >> 4)]; }
+  T* p;
+  __device__ __forceinline__ T& operator[](int i) const { return p[i + (i >> 4)]; }
 };
 
-__device__ __forceinline__ double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 c_mul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+template <class T>
+__device__ __forceinline__ Cx<T> c_add(Cx<T> a, Cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <class T>
+__device__ __forceinline__ Cx<T> c_sub(Cx<T> a, Cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <class T>
+__device__ __forceinline__ Cx<T> c_mul(Cx<T> a, Cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
-__device__ __forceinline__ double2 c_conj(double2 a) { return make_double2(a.x, -a.y); }
+template <class T>
+__device__ __forceinline__ Cx<T> c_conj(Cx<T> a) { return {a.x, -a.y}; }
 // multiply by SIGN * i
-template <int SIGN>
-__device__ __forceinline__ double2 c_rot(double2 a) {
-  return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+template <int SIGN, class T>
+__device__ __forceinline__ Cx<T> c_rot(Cx<T> a) {
+  return SIGN > 0 ? Cx<T>{-a.y, a.x} : Cx<T>{a.y, -a.x};
 }
 
 // in-register DFT of length R with kernel exp(SIGN 2 pi i t k / R)
-template <int R, int SIGN>
-__device__ __forceinline__ void dft_reg(double2* v) {
+template <int R, int SIGN, class T>
+__device__ __forceinline__ void dft_reg(Cx<T>* v) {
   if constexpr (R == 2) {
-    const double2 t = v[1];
+    const Cx<T> t = v[1];
     v[1] = c_sub(v[0], t);
     v[0] = c_add(v[0], t);
   } else if constexpr (R == 4) {
-    const double2 t0 = c_add(v[0], v[2]), t1 = c_sub(v[0], v[2]);
-    const double2 t2 = c_add(v[1], v[3]), t3 = c_rot<SIGN>(c_sub(v[1], v[3]));
+    const Cx<T> t0 = c_add(v[0], v[2]), t1 = c_sub(v[0], v[2]);
+    const Cx<T> t2 = c_add(v[1], v[3]), t3 = c_rot<SIGN>(c_sub(v[1], v[3]));
     v[0] = c_add(t0, t2);
     v[2] = c_sub(t0, t2);
     v[1] = c_add(t1, t3);
     v[3] = c_sub(t1, t3);
   } else {
     static_assert(R == 8, "radix");
-    double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    Cx<T> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
     dft_reg<4, SIGN>(e);
     dft_reg<4, SIGN>(o);
-    constexpr double h = 0.70710678118654752440;
+    constexpr T h = T(0.70710678118654752440);
+    constexpr T sg = T(SIGN);
     // o_k *= exp(SIGN 2 pi i k / 8)
-    o[1] = make_double2(h * (o[1].x - SIGN * o[1].y), h * (o[1].y + SIGN * o[1].x));
+    o[1] = Cx<T>{h * (o[1].x - sg * o[1].y), h * (o[1].y + sg * o[1].x)};
     o[2] = c_rot<SIGN>(o[2]);
-    o[3] = make_double2(h * (-o[3].x - SIGN * o[3].y), h * (-o[3].y + SIGN * o[3].x));
+    o[3] = Cx<T>{h * (-o[3].x - sg * o[3].y), h * (-o[3].y + sg * o[3].x)};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       v[k] = c_add(e[k], o[k]);
@@ -225,8 +270,8 @@ __device__ __forceinline__ void dft_reg(double2* v) {
 // Stockham passes from stride NS on.  On entry to the first pass (NS = 1)
 // a[t] holds element q + t P of the lane's transform; every pass leaves its
 // result in `buf` (M elements, natural order after the last pass).
-template <int M, int SIGN, int NS>
-__device__ __forceinline__ void fft_passes(double2* a, CBuf buf, int q, const double2* __restrict__ cs) {
+template <int M, int SIGN, int NS, class T>
+__device__ __forceinline__ void fft_passes(Cx<T>* a, CBuf<T> buf, int q, const Cx<T>* __restrict__ cs) {
   if constexpr (NS < M) {
     constexpr int RL = FdShape<M>::RL, P = FdShape<M>::P;
     constexpr int R = (M / NS) >= 8 ? 8 : (M / NS);
@@ -244,7 +289,7 @@ __device__ __forceinline__ void fft_passes(double2* a, CBuf buf, int q, const do
       if constexpr (NS > 1) {
 #pragma unroll
         for (int t = 1; t < R; ++t) {
-          double2 w = cs[2 * t * k * (M / (NS * R))];
+          Cx<T> w = cs[2 * t * k * (M / (NS * R))];
           if (SIGN > 0) w.y = -w.y;
           a[u * R + t] = c_mul(a[u * R + t], w);
         }
@@ -265,18 +310,18 @@ __device__ __forceinline__ void fft_passes(double2* a, CBuf buf, int q, const do
 }
 
 // segmented inclusive prefix sum over the P lanes of a slot
-template <int P>
-__device__ __forceinline__ double seg_scan(double v, int q) {
+template <int P, class T>
+__device__ __forceinline__ T seg_scan(T v, int q) {
 #pragma unroll
   for (int d = 1; d < P; d <<= 1) {
-    const double o = __shfl_up(v, d, P);
+    const T o = __shfl_up(v, d, P);
     if (q >= d) v += o;
   }
   return v;
 }
 
-template <int P>
-__device__ __forceinline__ double seg_sum(double v) {
+template <int P, class T>
+__device__ __forceinline__ T seg_sum(T v) {
 #pragma unroll
   for (int d = P >> 1; d > 0; d >>= 1) v += __shfl_xor(v, d, P);
   return v;
@@ -284,50 +329,50 @@ __device__ __forceinline__ double seg_sum(double v) {
 
 // DST-I pre-processing: a[t] = (y_{2e}, y_{2e+1}) for e = q + t P, x(j) for
 // 0 <= j <= N (zero at both ends)
-template <int M, class X>
-__device__ __forceinline__ void dst1_pre(double2* a, int q, const double* __restrict__ sn, X x) {
+template <int M, class T, class X>
+__device__ __forceinline__ void dst1_pre(Cx<T>* a, int q, const T* __restrict__ sn, X x) {
   constexpr int N = 2 * M, RL = FdShape<M>::RL, P = FdShape<M>::P;
 #pragma unroll
   for (int t = 0; t < RL; ++t) {
     const int e = q + t * P;
-    double y[2];
+    T y[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int j = 2 * e + h;
-      const double xa = x(j), xb = x(N - j);
-      y[h] = sn[j] * (xa + xb) + 0.5 * (xa - xb);
+      const T xa = x(j), xb = x(N - j);
+      y[h] = sn[j] * (xa + xb) + T(0.5) * (xa - xb);
     }
-    a[t] = make_double2(y[0], y[1]);
+    a[t] = Cx<T>{y[0], y[1]};
   }
 }
 
 // The real DFT bin k (0 <= k <= M) of the packed FFT Z: E + exp(-2 pi i k/N) O.
-template <int M>
-__device__ __forceinline__ double2 real_bin(CBuf Z, int k, const double2* __restrict__ cs) {
-  const double2 zk = Z[k & (M - 1)], zc = c_conj(Z[(M - k) & (M - 1)]);
-  const double2 e = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
-  const double2 d = c_sub(zk, zc);
-  const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);  // -i/2 (zk - zc)
-  double2 w = k < M ? cs[k] : make_double2(-1.0, 0.0);
+template <int M, class T>
+__device__ __forceinline__ Cx<T> real_bin(CBuf<T> Z, int k, const Cx<T>* __restrict__ cs) {
+  const Cx<T> zk = Z[k & (M - 1)], zc = c_conj(Z[(M - k) & (M - 1)]);
+  const Cx<T> e{T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y + zc.y)};
+  const Cx<T> d = c_sub(zk, zc);
+  const Cx<T> o{T(0.5) * d.y, T(-0.5) * d.x};  // -i/2 (zk - zc)
+  const Cx<T> w = k < M ? cs[k] : Cx<T>{T(-1), T(0)};
   return c_add(e, c_mul(w, o));
 }
 
 // DST-I post-processing: F_f (f = 1..N-1) into cv[f - 1] (cv aliases Z)
-template <int M>
-__device__ __forceinline__ void dst1_post(CBuf Z, RBuf cv, int q, const double2* __restrict__ cs) {
+template <int M, class T>
+__device__ __forceinline__ void dst1_post(CBuf<T> Z, RBuf<T> cv, int q, const Cx<T>* __restrict__ cs) {
   constexpr int RL = FdShape<M>::RL, P = FdShape<M>::P;
-  double R[RL], I[RL];
+  T R[RL], I[RL];
 #pragma unroll
   for (int s = 0; s < RL; ++s) {
     const int k = q * RL + s;
-    const double2 y = real_bin<M>(Z, k, cs);
-    R[s] = (k == 0) ? 0.5 * y.x : y.x;
+    const Cx<T> y = real_bin<M>(Z, k, cs);
+    R[s] = (k == 0) ? T(0.5) * y.x : y.x;
     I[s] = -y.y;
   }
 #pragma unroll
   for (int s = 1; s < RL; ++s) R[s] += R[s - 1];
-  const double tot = seg_scan<P>(R[RL - 1], q);
-  const double base = tot - R[RL - 1];
+  const T tot = seg_scan<P>(R[RL - 1], q);
+  const T base = tot - R[RL - 1];
   __syncthreads();  // every lane has read Z
 #pragma unroll
   for (int s = 0; s < RL; ++s) {
@@ -339,21 +384,21 @@ __device__ __forceinline__ void dst1_post(CBuf Z, RBuf cv, int q, const double2*
 }
 
 // DST-II post-processing: S_s (s = 1..N) into cv[s - 1]
-template <int M>
-__device__ __forceinline__ void dst2_post(CBuf Z, RBuf cv, int q, const double2* __restrict__ cs,
-                                          const double2* __restrict__ tq) {
+template <int M, class T>
+__device__ __forceinline__ void dst2_post(CBuf<T> Z, RBuf<T> cv, int q, const Cx<T>* __restrict__ cs,
+                                          const Cx<T>* __restrict__ tq) {
   constexpr int N = 2 * M, RL = FdShape<M>::RL;
-  double re[RL], im[RL];
-  double sm = 0.0;
+  T re[RL], im[RL];
+  T sm = T(0);
 #pragma unroll
   for (int s = 0; s < RL; ++s) {
     const int k = q * RL + s;
-    const double2 v = c_mul(tq[k], real_bin<M>(Z, k, cs));
+    const Cx<T> v = c_mul(tq[k], real_bin<M>(Z, k, cs));
     re[s] = v.x;
     im[s] = -v.y;
   }
   if (q == 0) {
-    const double2 z0 = Z[0];
+    const Cx<T> z0 = Z[0];
     sm = (tq[M].x * (z0.x - z0.y));  // Re(tq_M (Re Z_0 - Im Z_0))
   }
   __syncthreads();
@@ -369,19 +414,22 @@ __device__ __forceinline__ void dst2_post(CBuf Z, RBuf cv, int q, const double2*
 
 // Z = U~^T S column by column (Algorithm 4, step 5): t = E^T s staged in
 // LDS, the sine transform, times g; the V_2 coefficients are plain dot
-// products.
-template <int M, bool ODD>
+// products.  S and Z are FP64 in memory; T is the arithmetic type (the
+// loads are rounded to it, the results widened back).
+template <int M, bool ODD, class T>
 __global__ __launch_bounds__(kFdWave) void k_fd_forward(FdDev d, const double* __restrict__ S, int lds_, int r,
                                                         double* __restrict__ Zo) {
   constexpr int N = 2 * M, RL = FdShape<M>::RL, P = FdShape<M>::P, B = FdShape<M>::B;
   constexpr int SL = FdSlot<M>::SIZE;
-  __shared__ double2 sm[B * SL];
+  __shared__ Cx<T> sm[B * SL];
+  const FdTab<T>& tb = fd_tab<T>(d);
+  const Cx<T>* cs = reinterpret_cast<const Cx<T>*>(tb.cs);
   const int lane = threadIdx.x, b = lane / P, q = lane % P;
   const int c = blockIdx.x * B + b;
   const bool valid = c < r;
   const double* s = S + (long long)(valid ? c : r - 1) * lds_;
-  const CBuf Z{sm + b * SL};
-  const RBuf cv{reinterpret_cast<double*>(sm + b * SL)};
+  const CBuf<T> Z{sm + b * SL};
+  const RBuf<T> cv{reinterpret_cast<T*>(sm + b * SL)};
   // interior rows of E^T (a shifted copy): at most N = 2 RL P, 2 RL per lane;
   // the loads are clamped into range so that they issue together
   // the B input columns of the workgroup through one resource
@@ -393,81 +441,84 @@ __global__ __launch_bounds__(kFdWave) void k_fd_forward(FdDev d, const double* _
   for (int u = 0; u < 2 * RL; ++u) {
     const int m = q + P * u;
     const bool in = valid && m >= d.et_lo && m < d.et_hi;
-    cv[m] = buf_ld(rs, sb + m + d.et_sh, in);
+    cv[m] = T(buf_ld(rs, sb + m + d.et_sh, in));
   }
   // boundary rows [0, et_lo) and [et_hi, n1) through the ELL table, each by
   // the lane that wrote it above
   for (int m = q; m < d.n1; m += P) {
     if (m >= d.et_lo && m < d.et_hi) continue;
-    double t = 0.0;
+    T t = T(0);
     for (int k = 0; k < d.ket; ++k) {
       const int src = d.et_idx[m * d.ket + k];
-      if (src >= 0) t += d.et_val[m * d.ket + k] * s[src];
+      if (src >= 0) t += tb.et_val[m * d.ket + k] * T(s[src]);
     }
     cv[m] = t;
   }
   __syncthreads();
-  double2 a[RL];
+  Cx<T> a[RL];
   if constexpr (ODD) {
-    dst1_pre<M>(a, q, d.sn, [&](int j) {
-      const double x = cv[min(max(j - 1, 0), N - 2)];
-      return (j >= 1 && j < N) ? x : 0.0;
+    dst1_pre<M>(a, q, tb.sn, [&](int j) {
+      const T x = cv[min(max(j - 1, 0), N - 2)];
+      return (j >= 1 && j < N) ? x : T(0);
     });
   } else {
 #pragma unroll
     for (int t = 0; t < RL; ++t) {
       const int e = q + t * P;
-      double v[2];
+      T v[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int i = 2 * e + h;
         const int m = i < M ? 2 * i : 2 * N - 2 * i - 1;
         v[h] = (m & 1) ? -cv[m] : cv[m];
       }
-      a[t] = make_double2(v[0], v[1]);
+      a[t] = Cx<T>{v[0], v[1]};
     }
   }
   __syncthreads();  // the staged input is read before the first pass overwrites it
   if constexpr (ODD) {
-    fft_passes<M, -1, 1>(a, Z, q, d.cs);
-    dst1_post<M>(Z, cv, q, d.cs);
+    fft_passes<M, -1, 1>(a, Z, q, cs);
+    dst1_post<M>(Z, cv, q, cs);
   } else {
-    fft_passes<M, -1, 1>(a, Z, q, d.cs);
-    dst2_post<M>(Z, cv, q, d.cs, d.tq);
+    fft_passes<M, -1, 1>(a, Z, q, cs);
+    dst2_post<M>(Z, cv, q, cs, reinterpret_cast<const Cx<T>*>(tb.tq));
   }
   double* zc = Zo + (long long)c * d.n;
-  const auto rz = buf_rsrc(Zo + (long long)c0 * d.n, (long long)B * d.n), rg = buf_rsrc(d.g, d.n1);
+  const auto rz = buf_rsrc(Zo + (long long)c0 * d.n, (long long)B * d.n), rg = buf_rsrc(tb.g, d.n1);
 #pragma unroll
   for (int u = 0; u < 2 * RL; ++u) {
     const int mm = q + P * u;
     const bool ok = valid && mm < d.n1;
-    buf_st(rz, b * d.n + mm, ok, buf_ld(rg, mm, ok) * cv[mm]);
+    buf_st(rz, b * d.n + mm, ok, double(buf_ldt<T>(rg, mm, ok) * cv[mm]));
   }
   for (int a2 = 0; a2 < d.n2; ++a2) {
-    const double* v2 = d.v2u2 + (long long)a2 * d.n;
+    const T* v2 = tb.v2u2 + (long long)a2 * d.n;
     const auto rv = buf_rsrc(v2, d.n);
-    double part = 0.0;
+    T part = T(0);
 #pragma unroll
     for (int u = 0; u < 2 * RL; ++u) {
       const int i = q + P * u;
       const bool ok = i < d.n;
-      part += buf_ld(rv, i, ok) * buf_ld(rs, sb + i, ok && valid);
+      part += buf_ldt<T>(rv, i, ok) * T(buf_ld(rs, sb + i, ok && valid));
     }
-    for (int i = N + q; i < d.n; i += P) part += v2[i] * s[i];
+    for (int i = N + q; i < d.n; i += P) part += v2[i] * T(s[i]);
     part = seg_sum<P>(part);
-    if (valid && q == 0) zc[d.n1 + a2] = part;
+    if (valid && q == 0) zc[d.n1 + a2] = double(part);
   }
 }
 
 // Y[:, j r + c] = U~ D_j Z[:, c] (Algorithm 4, steps 7-8) for j in this
 // workgroup's range: the scaled coefficients staged in LDS, the inverse sine
-// transform, then E and the V_2 columns.
-template <int M, bool ODD>
+// transform, then E and the V_2 columns.  Z and Y are FP64 in memory; T is
+// the arithmetic type.
+template <int M, bool ODD, class T>
 __global__ __launch_bounds__(kFdWave) void k_fd_backward(FdDev d, const double* __restrict__ Zi, int r,
                                                          double* __restrict__ Y) {
   constexpr int N = 2 * M, RL = FdShape<M>::RL, P = FdShape<M>::P, B = FdShape<M>::B;
   constexpr int SL = FdSlot<M>::SIZE;
-  __shared__ double2 sm[B * SL];
+  __shared__ Cx<T> sm[B * SL];
+  const FdTab<T>& tb = fd_tab<T>(d);
+  const Cx<T>* cs = reinterpret_cast<const Cx<T>*>(tb.cs);
   const int lane = threadIdx.x, b = lane / P, q = lane % P;
   // the R_P terms of one column run in consecutive logical workgroups on one
   // XCD (the column is then read from that XCD's L2 after the first)
@@ -477,11 +528,10 @@ __global__ __launch_bounds__(kFdWave) void k_fd_backward(FdDev d, const double* 
   const int j = jg * B + b;
   const bool valid = j < d.R;
   const double* zc = Zi + (long long)c * d.n;
-  const CBuf Z{sm + b * SL};
-  const RBuf cv{reinterpret_cast<double*>(sm + b * SL)};
+  const CBuf<T> Z{sm + b * SL};
+  const RBuf<T> cv{reinterpret_cast<T*>(sm + b * SL)};
   {
-    const double* ge = d.ge + (long long)(valid ? j : d.R - 1) * d.n;
-    const auto rg = buf_rsrc(d.ge, (long long)d.R * d.n), rz = buf_rsrc(zc, d.n);
+    const auto rg = buf_rsrc(tb.ge, (long long)d.R * d.n), rz = buf_rsrc(zc, d.n);
     const int gb = (valid ? j : 0) * d.n;
     // w_m = ge_m z_m for m < N (for odd p the entry m = n1 = N - 1 is a V_2
     // coefficient the transform never reads)
@@ -489,50 +539,51 @@ __global__ __launch_bounds__(kFdWave) void k_fd_backward(FdDev d, const double* 
     for (int u = 0; u < 2 * RL; ++u) {
       const int m = q + P * u;
       const bool ok = m < d.n;
-      cv[m] = buf_ld(rg, gb + m, ok) * buf_ld(rz, m, ok);
+      cv[m] = buf_ldt<T>(rg, gb + m, ok) * T(buf_ld(rz, m, ok));
     }
-    double w2[kFdMaxV2];
+    T w2[kFdMaxV2];
 #pragma unroll
     for (int a2 = 0; a2 < kFdMaxV2; ++a2) {
       const bool ok = a2 < d.n2;
-      w2[a2] = buf_ld(rg, gb + d.n1 + a2, ok) * buf_ld(rz, d.n1 + a2, ok);
+      w2[a2] = buf_ldt<T>(rg, gb + d.n1 + a2, ok) * T(buf_ld(rz, d.n1 + a2, ok));
     }
     __syncthreads();
-    double2 a[RL];
+    Cx<T> a[RL];
     if constexpr (ODD) {
-      dst1_pre<M>(a, q, d.sn, [&](int jj) {
-        const double x = cv[min(max(jj - 1, 0), N - 2)];
-        return (jj >= 1 && jj < N) ? x : 0.0;
+      dst1_pre<M>(a, q, tb.sn, [&](int jj) {
+        const T x = cv[min(max(jj - 1, 0), N - 2)];
+        return (jj >= 1 && jj < N) ? x : T(0);
       });
     } else {
       // inverse of the DST-II steps on S_s = w_{s-1}, the last one doubled
+      const Cx<T>* tq = reinterpret_cast<const Cx<T>*>(tb.tq);
 #pragma unroll
       for (int t = 0; t < RL; ++t) {
         const int k = q + t * P, km = M - k, k1 = max(k, 1);
-        const double sN = cv[N - 1], sa = cv[N - k1 - 1], sb = cv[k1 - 1];
-        const double2 qk = k == 0 ? make_double2(2.0 * sN, 0.0) : make_double2(sa, -sb);
-        const double2 qm = make_double2(cv[N - km - 1], -cv[km - 1]);
-        const double2 vk = c_mul(c_conj(d.tq[k]), qk), vm = c_conj(c_mul(c_conj(d.tq[km]), qm));
-        const double2 e = make_double2(0.5 * (vk.x + vm.x), 0.5 * (vk.y + vm.y));
-        const double2 o = c_mul(make_double2(0.5 * (vk.x - vm.x), 0.5 * (vk.y - vm.y)), c_conj(d.cs[k]));
-        a[t] = make_double2(e.x - o.y, e.y + o.x);  // e + i o
+        const T sN = cv[N - 1], sa = cv[N - k1 - 1], sb = cv[k1 - 1];
+        const Cx<T> qk = k == 0 ? Cx<T>{T(2) * sN, T(0)} : Cx<T>{sa, -sb};
+        const Cx<T> qm{cv[N - km - 1], -cv[km - 1]};
+        const Cx<T> vk = c_mul(c_conj(tq[k]), qk), vm = c_conj(c_mul(c_conj(tq[km]), qm));
+        const Cx<T> e{T(0.5) * (vk.x + vm.x), T(0.5) * (vk.y + vm.y)};
+        const Cx<T> o = c_mul(Cx<T>{T(0.5) * (vk.x - vm.x), T(0.5) * (vk.y - vm.y)}, c_conj(cs[k]));
+        a[t] = Cx<T>{e.x - o.y, e.y + o.x};  // e + i o
       }
     }
     __syncthreads();  // the staged input is read before the first pass overwrites it
     if constexpr (ODD) {
-      fft_passes<M, -1, 1>(a, Z, q, d.cs);
-      dst1_post<M>(Z, cv, q, d.cs);
+      fft_passes<M, -1, 1>(a, Z, q, cs);
+      dst1_post<M>(Z, cv, q, cs);
     } else {
-      fft_passes<M, 1, 1>(a, Z, q, d.cs);
+      fft_passes<M, 1, 1>(a, Z, q, cs);
       // v = the FFT output read as N reals (v_{2i} = Re z_i, v_{2i+1} = Im z_i);
       // T_m = (-1)^m v[m even ? m/2 : N-1-(m-1)/2]
-      double tv[2 * RL];
+      T tv[2 * RL];
 #pragma unroll
       for (int u = 0; u < 2 * RL; ++u) {
         const int m = q + P * u;
         const int i = (m & 1) ? N - 1 - (m >> 1) : (m >> 1);
-        const double2 zi = Z[i >> 1];
-        const double x = (i & 1) ? zi.y : zi.x;
+        const Cx<T> zi = Z[i >> 1];
+        const T x = (i & 1) ? zi.y : zi.x;
         tv[u] = (m & 1) ? -x : x;
       }
       __syncthreads();
@@ -542,10 +593,10 @@ __global__ __launch_bounds__(kFdWave) void k_fd_backward(FdDev d, const double* 
     }
     double* yc = Y + ((long long)(valid ? j : 0) * r + c) * d.n;
     auto v2 = [&](int l) {
-      double acc = 0.0;
+      T acc = T(0);
 #pragma unroll
       for (int a2 = 0; a2 < kFdMaxV2; ++a2)
-        if (a2 < d.n2) acc += d.v2u2[l + (long long)a2 * d.n] * w2[a2];
+        if (a2 < d.n2) acc += tb.v2u2[l + (long long)a2 * d.n] * w2[a2];
       return acc;
     };
     // interior rows of E (a shifted copy): at most N = 2 RL P, 2 RL per lane,
@@ -555,31 +606,31 @@ __global__ __launch_bounds__(kFdWave) void k_fd_backward(FdDev d, const double* 
       const int j0 = jg * B;
       const auto ry = buf_rsrc(Y + ((long long)j0 * r + c) * d.n, ((long long)(B - 1) * r + 1) * d.n);
       const int yb = b * r * d.n;
-      double acc[2 * RL];
+      T acc[2 * RL];
 #pragma unroll
       for (int u = 0; u < 2 * RL; ++u) acc[u] = cv[min(d.e_lo + q + P * u, d.e_hi - 1) + d.e_sh];
 #pragma unroll
       for (int a2 = 0; a2 < kFdMaxV2; ++a2) {
         if (a2 < d.n2) {  // uniform
-          const auto rv = buf_rsrc(d.v2u2 + (long long)a2 * d.n, d.n);
+          const auto rv = buf_rsrc(tb.v2u2 + (long long)a2 * d.n, d.n);
 #pragma unroll
-          for (int u = 0; u < 2 * RL; ++u) acc[u] += buf_ld(rv, d.e_lo + q + P * u, true) * w2[a2];
+          for (int u = 0; u < 2 * RL; ++u) acc[u] += buf_ldt<T>(rv, d.e_lo + q + P * u, true) * w2[a2];
         }
       }
 #pragma unroll
       for (int u = 0; u < 2 * RL; ++u) {
         const int l = d.e_lo + q + P * u;
-        buf_st(ry, yb + l, valid && l < d.e_hi, acc[u]);
+        buf_st(ry, yb + l, valid && l < d.e_hi, double(acc[u]));
       }
     }
     // boundary rows [0, e_lo) and [e_hi, n) through the ELL table
     auto ell = [&](int l) {
-      double acc = 0.0;
+      T acc = T(0);
       for (int k = 0; k < d.ke; ++k) {
         const int src = d.e_idx[l * d.ke + k];
-        if (src >= 0) acc += d.e_val[l * d.ke + k] * cv[src];
+        if (src >= 0) acc += tb.e_val[l * d.ke + k] * cv[src];
       }
-      if (valid) yc[l] = acc + v2(l);
+      if (valid) yc[l] = double(acc + v2(l));
     };
     for (int l = q; l < d.e_lo; l += P) ell(l);
     for (int l = d.e_hi + q; l < d.n; l += P) ell(l);
@@ -591,54 +642,64 @@ static void fd_check_span(long long doubles, const char* what) {
   if (doubles * 8 >= (long long)kBufOffHost) throw std::runtime_error(std::string(what) + ": more than 4 GB in one workgroup's reach");
 }
 
-template <int M>
+template <int M, class T>
 static void fd_forward_m(hipStream_t s, const FdDev& d, const double* S, int lds_, int r, double* Z) {
   constexpr int B = FdShape<M>::B;
   fd_check_span((long long)B * lds_ + d.n, "fd_forward");
   const dim3 grid((r + B - 1) / B);
   if (d.odd)
-    hipLaunchKernelGGL((k_fd_forward<M, true>), grid, dim3(kFdWave), 0, s, d, S, lds_, r, Z);
+    hipLaunchKernelGGL((k_fd_forward<M, true, T>), grid, dim3(kFdWave), 0, s, d, S, lds_, r, Z);
   else
-    hipLaunchKernelGGL((k_fd_forward<M, false>), grid, dim3(kFdWave), 0, s, d, S, lds_, r, Z);
+    hipLaunchKernelGGL((k_fd_forward<M, false, T>), grid, dim3(kFdWave), 0, s, d, S, lds_, r, Z);
 }
 
-template <int M>
+template <int M, class T>
 static void fd_backward_m(hipStream_t s, const FdDev& d, const double* Z, int r, double* Y) {
   constexpr int B = FdShape<M>::B;
   fd_check_span((long long)B * r * d.n + (long long)d.R * d.n, "fd_backward");
   const dim3 grid((unsigned)r * ((d.R + B - 1) / B));
   if (d.odd)
-    hipLaunchKernelGGL((k_fd_backward<M, true>), grid, dim3(kFdWave), 0, s, d, Z, r, Y);
+    hipLaunchKernelGGL((k_fd_backward<M, true, T>), grid, dim3(kFdWave), 0, s, d, Z, r, Y);
   else
-    hipLaunchKernelGGL((k_fd_backward<M, false>), grid, dim3(kFdWave), 0, s, d, Z, r, Y);
+    hipLaunchKernelGGL((k_fd_backward<M, false, T>), grid, dim3(kFdWave), 0, s, d, Z, r, Y);
 }
 
-#define TK_FD_DISPATCH(FN, ...)                                            \
+#define TK_FD_DISPATCH(FN, T, ...)                                         \
   switch (d.N) {                                                           \
-    case 4: FN<2>(__VA_ARGS__); break;                                     \
-    case 8: FN<4>(__VA_ARGS__); break;                                     \
-    case 16: FN<8>(__VA_ARGS__); break;                                    \
-    case 32: FN<16>(__VA_ARGS__); break;                                   \
-    case 64: FN<32>(__VA_ARGS__); break;                                   \
-    case 128: FN<64>(__VA_ARGS__); break;                                  \
-    case 256: FN<128>(__VA_ARGS__); break;                                 \
-    case 512: FN<256>(__VA_ARGS__); break;                                 \
-    case 1024: FN<512>(__VA_ARGS__); break;                                \
+    case 4: FN<2, T>(__VA_ARGS__); break;                                  \
+    case 8: FN<4, T>(__VA_ARGS__); break;                                  \
+    case 16: FN<8, T>(__VA_ARGS__); break;                                 \
+    case 32: FN<16, T>(__VA_ARGS__); break;                                \
+    case 64: FN<32, T>(__VA_ARGS__); break;                                \
+    case 128: FN<64, T>(__VA_ARGS__); break;                               \
+    case 256: FN<128, T>(__VA_ARGS__); break;                              \
+    case 512: FN<256, T>(__VA_ARGS__); break;                              \
+    case 1024: FN<512, T>(__VA_ARGS__); break;                             \
     default: throw std::runtime_error("fd: transform length must be a power of two in [4, 1024]"); \
   }
 
-void fd_forward(hipStream_t s, const FdDev& d, const double* S, int lds_, int r, double* Z) {
+void fd_forward(hipStream_t s, const FdDev& d, const double* S, int lds_, int r, double* Z, bool f32) {
   if (r <= 0) return;
   if (d.n2 > kFdMaxV2) throw std::runtime_error("fd_forward: more than 4 V_2 columns (degree above 6)");
-  TK_FD_DISPATCH(fd_forward_m, s, d, S, lds_, r, Z);
+  if (f32) {
+    if (!d.t32.g) throw std::runtime_error("fd_forward: no single-precision tables");
+    TK_FD_DISPATCH(fd_forward_m, float, s, d, S, lds_, r, Z);
+  } else {
+    TK_FD_DISPATCH(fd_forward_m, double, s, d, S, lds_, r, Z);
+  }
   check_launch("fd_forward");
 }
 
-void fd_backward(hipStream_t s, const FdDev& d, const double* Z, int r, double* Y) {
+void fd_backward(hipStream_t s, const FdDev& d, const double* Z, int r, double* Y, bool f32) {
   if (r <= 0 || d.R <= 0) return;
   if (d.n2 > kFdMaxV2) throw std::runtime_error("fd_backward: more than 4 V_2 columns (degree above 6)");
   if (d.R > 65535) throw std::runtime_error("fd_backward: more than 65535 exponential-sum terms");
-  TK_FD_DISPATCH(fd_backward_m, s, d, Z, r, Y);
+  if (f32) {
+    if (!d.t32.g) throw std::runtime_error("fd_backward: no single-precision tables");
+    TK_FD_DISPATCH(fd_backward_m, float, s, d, Z, r, Y);
+  } else {
+    TK_FD_DISPATCH(fd_backward_m, double, s, d, Z, r, Y);
+  }
   check_launch("fd_backward");
 }
 

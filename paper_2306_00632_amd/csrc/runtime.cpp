@@ -153,6 +153,7 @@ struct tk_op {
   int n[3] = {0, 0, 0};
   int nmat[3] = {0, 0, 0};
   tk::BufP band[3];
+  tk::BufP band_f[3];  // the same bands rounded to FP32 (for FP32 arithmetic)
   std::vector<tk_core_nz> nz;
 };
 
@@ -163,6 +164,7 @@ struct tk_prec {
   tk::FdDirection dir[3];
   tk::BufP g[3], e_val[3], et_val[3], v2u2[3], ge[3], cs[3], sn[3], tq[3];
   tk::BufP e_idx[3], et_idx[3];  // stored as ints inside double buffers
+  tk::BufP f32[3];               // the real tables rounded to FP32, one buffer per direction
   tk::gpu::FdDev dev[3];
   // exact-eigenvector variant (fd_setup_exact): dense M-orthonormal U_k
   // (n_k x n_k) and E_k[j, m] = exp(-alpha_j lam_m / lam_min) (R x n_k)
@@ -695,7 +697,7 @@ static double core_norm(tk_ctx* ctx, const tk_tucker* t) {
 // operator application (eq. tt_product)
 // ---------------------------------------------------------------------------
 
-static tk_tucker* apply_op(tk_ctx* ctx, const tk_op* op, const tk_tucker* x) {
+static tk_tucker* apply_op(tk_ctx* ctx, const tk_op* op, const tk_tucker* x, bool f32 = false) {
   for (int k = 0; k < 3; ++k)
     if (x->n[k] != op->n[k]) throw Error(TK_EINVAL, "operator and tensor sizes differ");
   auto* t = new tk_tucker;
@@ -705,8 +707,9 @@ static tk_tucker* apply_op(tk_ctx* ctx, const tk_op* op, const tk_tucker* x) {
     t->U[k] = alloc(ctx, (size_t)t->n[k] * t->m[k]);
     const double nn = x->n[k], mm = x->m[k], R = op->nmat[k], nb = 2 * op->p + 1;
     Prof pr(ctx, PK_BAND, 8.0 * (nn * mm + R * nb * nn + R * nn * mm), 2.0 * R * nb * nn * mm);
-    gpu::band_apply(ctx->stream, x->n[k], x->m[k], op->nmat[k], op->p, op->band[k]->p, x->U[k]->p,
-                    x->n[k], t->U[k]->p, t->n[k]);
+    gpu::band_apply(ctx->stream, x->n[k], x->m[k], op->nmat[k], op->p, op->band[k]->p,
+                    f32 ? reinterpret_cast<const float*>(op->band_f[k]->p) : nullptr, x->U[k]->p, x->n[k],
+                    t->U[k]->p, t->n[k]);
   }
   for (const auto& z : op->nz)
     for (const auto& b : x->blocks) {
@@ -724,7 +727,9 @@ static tk_tucker* apply_op(tk_ctx* ctx, const tk_op* op, const tk_tucker* x) {
 // low-rank FD application (Algorithm 4, steps 5-9)
 // ---------------------------------------------------------------------------
 
-static tk_tucker* apply_prec(tk_ctx* ctx, const tk_prec* P, const tk_tucker* s) {
+// f32: FP32 arithmetic in the transforms (the exact-eigenvector variant
+// always runs in FP64)
+static tk_tucker* apply_prec(tk_ctx* ctx, const tk_prec* P, const tk_tucker* s, bool f32 = false) {
   if (s->blocks.size() != 1) throw Error(TK_EINVAL, "fd_precond expects a plain (truncated) Tucker tensor");
   for (int k = 0; k < 3; ++k)
     if (s->n[k] != (P->exact ? P->n_exact[k] : P->dir[k].n))
@@ -769,13 +774,13 @@ static tk_tucker* apply_prec(tk_ctx* ctx, const tk_prec* P, const tk_tucker* s) 
     {
       // algorithmic bytes: read S, write Z, boundary map and V2U2 columns
       Prof pr(ctx, PK_FD_FWD, 8.0 * (2.0 * n * r + (double)n * d.n2), r * (fft + 2.0 * n * (1 + d.n2)));
-      gpu::fd_forward(ctx->stream, d, s->U[k]->p, n, r, Z->p);
+      gpu::fd_forward(ctx->stream, d, s->U[k]->p, n, r, Z->p, f32);
     }
     {
       // read Z and the exp table, write R_P r columns
       Prof pr(ctx, PK_FD_BWD, 8.0 * ((double)n * r + (double)P->R * n + (double)P->R * n * r + (double)n * d.n2),
               (double)P->R * r * (fft + n * (1.0 + 2.0 * d.n2)));
-      gpu::fd_backward(ctx->stream, d, Z->p, r, t->U[k]->p);
+      gpu::fd_backward(ctx->stream, d, Z->p, r, t->U[k]->p, f32);
     }
   }
   for (int j = 0; j < P->R; ++j) {
@@ -812,6 +817,16 @@ static tk_tucker* scaled_copy(tk_ctx* ctx, const tk_tucker* x, double a) {
   return t;
 }
 
+// Precision rule of the mixed mode: the preconditioner application z = P(r)
+// and the operator application q = A p (which only steer the search
+// direction; the residual is recomputed from x) may run in FP32 arithmetic
+// when the relative tolerance eta_k of the truncation that follows is at
+// least 10 times the FP32 unit roundoff 2^-24; the update of x, the residual
+// f - A x, the scalar products and every truncation stay FP64.
+static bool arith_f32(const tk_tpcg_params& prm, double eta) {
+  return prm.arith == TK_ARITH_MIXED && eta >= 10.0 * 0x1p-24;
+}
+
 static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_tucker* f_in,
                       const tk_tpcg_params& prm, tk_tucker** x_out, tk_tpcg_info* info) {
   tk_tpcg_info inf{};
@@ -836,11 +851,16 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
     nr = core_norm(ctx, r.t);
   }
   double eta = beta * tol / nr;
-  Owned pz(apply_prec(ctx, P, r.t));
+  auto f32 = [&]() {
+    const bool on = arith_f32(prm, eta);
+    inf.f32_applications += on ? 1 : 0;
+    return on;
+  };
+  Owned pz(apply_prec(ctx, P, r.t, f32()));
   Owned z(truncate(ctx, pz.t, eta, nullptr));
   pz = Owned();
   Owned p(scaled_copy(ctx, z.t, 1.0));
-  Owned ap(apply_op(ctx, op, p.t));
+  Owned ap(apply_op(ctx, op, p.t, f32()));
   Owned q(truncate(ctx, ap.t, eta, nullptr));
   ap = Owned();
   inf.trel_calls = 2;
@@ -886,14 +906,14 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
     if (!std::isfinite(nr)) { st = TK_EBREAKDOWN; break; }
     if (nr <= tol) break;
     eta = beta * tol / nr;
-    pz = Owned(apply_prec(ctx, P, r.t));
+    pz = Owned(apply_prec(ctx, P, r.t, f32()));
     z = Owned(truncate(ctx, pz.t, eta, nullptr));
     pz = Owned();
     const double bk = -dot(ctx, z.t, q.t) / xi;
     Owned zp(lin_comb(ctx, 1.0, z.t, bk, p.t));
     p = Owned(truncate(ctx, zp.t, eta, nullptr));
     zp = Owned();
-    ap = Owned(apply_op(ctx, op, p.t));
+    ap = Owned(apply_op(ctx, op, p.t, f32()));
     q = Owned(truncate(ctx, ap.t, eta, nullptr));
     ap = Owned();
     xi = dot(ctx, p.t, q.t);
@@ -919,12 +939,13 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
 // ---------------------------------------------------------------------------
 
 // y_a = sum_b A_ab x_b (A row-major 3 x 3, null = zero block)
-static void apply_op_block(tk_ctx* ctx, const tk_op* const A[9], tk_tucker* const x[3], Owned y[3]) {
+static void apply_op_block(tk_ctx* ctx, const tk_op* const A[9], tk_tucker* const x[3], Owned y[3],
+                           bool f32 = false) {
   for (int a = 0; a < 3; ++a) {
     Owned acc;
     for (int b = 0; b < 3; ++b) {
       if (!A[3 * a + b]) continue;
-      Owned t(apply_op(ctx, A[3 * a + b], x[b]));
+      Owned t(apply_op(ctx, A[3 * a + b], x[b], f32));
       acc = acc.t ? Owned(lin_comb(ctx, 1.0, acc.t, 1.0, t.t)) : std::move(t);
     }
     if (!acc.t) {
@@ -985,18 +1006,23 @@ static tk_status tpcg_block(tk_ctx* ctx, const tk_op* const A[9], const tk_prec*
     nr = tnorm(r);
   }
   double eta = beta * tol / nr;
+  // the precision rule of tpcg: P(r) and A p in FP32 arithmetic when allowed
   auto precond = [&](Owned* s, Owned* out) {
-    for (int a = 0; a < 3; ++a) out[a] = Owned(apply_prec(ctx, P[a], s[a].t));
+    const bool f32 = arith_f32(prm, eta);
+    inf.f32_applications += f32 ? 1 : 0;
+    for (int a = 0; a < 3; ++a) out[a] = Owned(apply_prec(ctx, P[a], s[a].t, f32));
   };
-  auto op_apply = [&](Owned* v, Owned* out) {
+  auto op_apply = [&](Owned* v, Owned* out, bool direction) {
+    const bool f32 = direction && arith_f32(prm, eta);
+    inf.f32_applications += f32 ? 1 : 0;
     tk_tucker* vr[3];
     raw(v, vr);
-    apply_op_block(ctx, A, vr, out);
+    apply_op_block(ctx, A, vr, out, f32);
   };
   precond(r, tmp);
   trunc(tmp, eta, z);
   for (int a = 0; a < 3; ++a) p[a] = Owned(scaled_copy(ctx, z[a].t, 1.0));
-  op_apply(p, tmp);
+  op_apply(p, tmp, true);
   trunc(tmp, eta, q);
   double xi = bdot(p, q);
   double eps = prm.eps0;
@@ -1032,7 +1058,7 @@ static tk_status tpcg_block(tk_ctx* ctx, const tk_op* const A[9], const tk_prec*
       yt[a] = Owned();
     }
     // r_{k+1} = T^rel(f - A x_{k+1}, eta_k)
-    op_apply(x, tmp);
+    op_apply(x, tmp, false);
     Owned res[3];
     for (int a = 0; a < 3; ++a) {
       res[a] = Owned(lin_comb(ctx, 1.0, f[a].t, -1.0, tmp[a].t));
@@ -1052,7 +1078,7 @@ static tk_status tpcg_block(tk_ctx* ctx, const tk_op* const A[9], const tk_prec*
     const double bk = -bdot(z, q) / xi;
     for (int a = 0; a < 3; ++a) tmp[a] = Owned(lin_comb(ctx, 1.0, z[a].t, bk, p[a].t));
     trunc(tmp, eta, p);
-    op_apply(p, tmp);
+    op_apply(p, tmp, true);
     trunc(tmp, eta, q);
     xi = bdot(p, q);
   }
@@ -1326,6 +1352,10 @@ tk_status tk_op_create(tk_ctx* ctx, int32_t p, const int64_t n[3], const int32_t
       const size_t cnt = (size_t)nmat[k] * (2 * p + 1) * n[k];
       op->band[k] = alloc(ctx, cnt);
       h2d(ctx, op->band[k]->p, bands[k], cnt);
+      std::vector<float> bf(bands[k], bands[k] + cnt);
+      op->band_f[k] = alloc(ctx, (cnt + 1) / 2);
+      HIPCHK(hipMemcpyAsync(op->band_f[k]->p, bf.data(), cnt * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+      sync(ctx);
     }
     for (int64_t i = 0; i < nnz; ++i) {
       if (nz[i].i1 < 0 || nz[i].i1 >= nmat[0] || nz[i].i2 < 0 || nz[i].i2 >= nmat[1] || nz[i].i3 < 0 ||
@@ -1344,6 +1374,12 @@ tk_status tucker_apply_op(tk_ctx* ctx, const tk_op* op, const tk_tucker* x, tk_t
   if (!ctx || !op || !x || !y) return TK_EINVAL;
   *y = nullptr;
   return guarded(ctx, [&]() { *y = apply_op(ctx, op, x); return TK_OK; });
+}
+
+tk_status tucker_apply_op_arith(tk_ctx* ctx, const tk_op* op, const tk_tucker* x, int32_t arith, tk_tucker** y) {
+  if (!ctx || !op || !x || !y || (arith != TK_ARITH_F64 && arith != TK_ARITH_F32)) return TK_EINVAL;
+  *y = nullptr;
+  return guarded(ctx, [&]() { *y = apply_op(ctx, op, x, arith == TK_ARITH_F32); return TK_OK; });
 }
 
 // The widest range [lo, hi) of rows around the middle of an ELL matrix whose
@@ -1443,16 +1479,42 @@ tk_status fd_setup(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_pre
       dv.ke = d.ke;
       dv.ket = d.ket;
       dv.R = P->R;
-      dv.g = P->g[k]->p;
       dv.e_idx = reinterpret_cast<const int*>(P->e_idx[k]->p);
-      dv.e_val = P->e_val[k]->p;
       dv.et_idx = reinterpret_cast<const int*>(P->et_idx[k]->p);
-      dv.et_val = P->et_val[k]->p;
-      dv.v2u2 = P->v2u2[k]->p;
-      dv.ge = P->ge[k]->p;
-      dv.cs = reinterpret_cast<const double2*>(P->cs[k]->p);
-      dv.sn = P->sn[k]->p;
-      dv.tq = reinterpret_cast<const double2*>(P->tq[k]->p);
+      dv.t64.g = P->g[k]->p;
+      dv.t64.e_val = P->e_val[k]->p;
+      dv.t64.et_val = P->et_val[k]->p;
+      dv.t64.v2u2 = P->v2u2[k]->p;
+      dv.t64.ge = P->ge[k]->p;
+      dv.t64.cs = P->cs[k]->p;
+      dv.t64.sn = P->sn[k]->p;
+      dv.t64.tq = P->tq[k]->p;
+      {
+        // the same tables rounded to FP32, packed in one buffer (each table
+        // starts on a 16-byte boundary)
+        const std::vector<double>* tabs[8] = {&d.g, &d.e_val, &d.et_val, &d.v2u2, &ge, &cs, &sn, &tq};
+        size_t off[8], tot = 0;
+        for (int i = 0; i < 8; ++i) {
+          off[i] = tot;
+          tot += (tabs[i]->size() + 3) / 4 * 4;
+        }
+        std::vector<float> hf(std::max<size_t>(tot, 4), 0.0f);
+        for (int i = 0; i < 8; ++i)
+          for (size_t e = 0; e < tabs[i]->size(); ++e) hf[off[i] + e] = float((*tabs[i])[e]);
+        P->f32[k] = alloc(ctx, (hf.size() + 1) / 2);
+        HIPCHK(hipMemcpyAsync(P->f32[k]->p, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice,
+                              ctx->stream));
+        sync(ctx);
+        const float* fb = reinterpret_cast<const float*>(P->f32[k]->p);
+        dv.t32.g = fb + off[0];
+        dv.t32.e_val = fb + off[1];
+        dv.t32.et_val = fb + off[2];
+        dv.t32.v2u2 = fb + off[3];
+        dv.t32.ge = fb + off[4];
+        dv.t32.cs = fb + off[5];
+        dv.t32.sn = fb + off[6];
+        dv.t32.tq = fb + off[7];
+      }
       interior_rows(d.e_idx, d.e_val, d.ke, d.n, dv.e_lo, dv.e_hi, dv.e_sh);
       interior_rows(d.et_idx, d.et_val, d.ket, d.n1, dv.et_lo, dv.et_hi, dv.et_sh);
     }
@@ -1566,6 +1628,12 @@ tk_status fd_precond(tk_ctx* ctx, const tk_prec* P, const tk_tucker* s, tk_tucke
   return guarded(ctx, [&]() { *v = apply_prec(ctx, P, s); return TK_OK; });
 }
 
+tk_status fd_precond_arith(tk_ctx* ctx, const tk_prec* P, const tk_tucker* s, int32_t arith, tk_tucker** v) {
+  if (!ctx || !P || !s || !v || (arith != TK_ARITH_F64 && arith != TK_ARITH_F32)) return TK_EINVAL;
+  *v = nullptr;
+  return guarded(ctx, [&]() { *v = apply_prec(ctx, P, s, arith == TK_ARITH_F32); return TK_OK; });
+}
+
 tk_status tucker_truncate(tk_ctx* ctx, const tk_tucker* y, double eps, tk_tucker** out, double* discarded) {
   if (!ctx || !y || !out || !(eps >= 0.0)) return TK_EINVAL;
   *out = nullptr;
@@ -1656,7 +1724,8 @@ tk_status tpcg_solve_block(tk_ctx* ctx, const tk_op* const A[9], const tk_prec* 
   tk_tpcg_params prm;
   tk_tpcg_defaults(&prm);
   if (params) prm = *params;
-  if (!(prm.tol > 0) || !(prm.alpha > 0 && prm.alpha < 1) || !(prm.eps0 > 0) || prm.maxit < 1)
+  if (!(prm.tol > 0) || !(prm.alpha > 0 && prm.alpha < 1) || !(prm.eps0 > 0) || prm.maxit < 1 ||
+      (prm.arith != TK_ARITH_F64 && prm.arith != TK_ARITH_MIXED))
     return TK_EINVAL;
   for (int a = 0; a < 3; ++a) x[a] = nullptr;
   return guarded(ctx, [&]() { return tpcg_block(ctx, A, P, f, prm, x, info); });
@@ -1687,6 +1756,7 @@ void tk_tpcg_defaults(tk_tpcg_params* p) {
   p->delta = 1e-3;
   p->maxit = 1000;
   p->verbose = 0;
+  p->arith = TK_ARITH_F64;
 }
 
 tk_status tpcg_solve(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_tucker* f,
@@ -1697,7 +1767,7 @@ tk_status tpcg_solve(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_tu
   if (params) prm = *params;
   else tk_tpcg_defaults(&prm);
   if (!(prm.tol > 0) || !(prm.beta > 0) || !(prm.eps0 > 0) || !(prm.alpha > 0 && prm.alpha < 1) ||
-      !(prm.delta > 0) || prm.maxit < 0) {
+      !(prm.delta > 0) || prm.maxit < 0 || (prm.arith != TK_ARITH_F64 && prm.arith != TK_ARITH_MIXED)) {
     ctx->last_error = "tpcg_solve: invalid parameters";
     return TK_EINVAL;
   }

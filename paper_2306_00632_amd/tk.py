@@ -36,12 +36,13 @@ class CoreNz(C.Structure):
 class TpcgParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("beta", C.c_double), ("eps0", C.c_double),
                 ("alpha", C.c_double), ("eps_min", C.c_double), ("delta", C.c_double),
-                ("maxit", C.c_int32), ("verbose", C.c_int32)]
+                ("maxit", C.c_int32), ("verbose", C.c_int32), ("arith", C.c_int32)]
 
 
 class TpcgInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double),
-                ("rank", C.c_int64 * 3), ("eps_final", C.c_double), ("trel_calls", C.c_int32)]
+                ("rank", C.c_int64 * 3), ("eps_final", C.c_double), ("trel_calls", C.c_int32),
+                ("f32_applications", C.c_int32)]
 
 
 EXPORTS = {
@@ -65,12 +66,14 @@ EXPORTS = {
                                  C.c_int64, C.POINTER(vp)]),
     "tk_op_free": (None, [vp]),
     "tucker_apply_op": (C.c_int32, [vp, vp, vp, C.POINTER(vp)]),
+    "tucker_apply_op_arith": (C.c_int32, [vp, vp, vp, C.c_int32, C.POINTER(vp)]),
     "fd_setup": (C.c_int32, [vp, i32p, C.c_int32, C.c_double, dp, C.POINTER(vp), i32p]),
     "fd_setup_exact": (C.c_int32, [vp, i32p, C.c_int32, C.c_double, dp, C.POINTER(vp), i32p]),
     "tk_prec_free": (None, [vp]),
     "tk_prec_info": (C.c_int32, [vp, i32p, dp, dp, dp, dp, dp]),
     "tk_prec_direction": (C.c_int32, [vp, C.c_int32, i32p, i32p, i32p, dp, dp, dp, dp]),
     "fd_precond": (C.c_int32, [vp, vp, vp, C.POINTER(vp)]),
+    "fd_precond_arith": (C.c_int32, [vp, vp, vp, C.c_int32, C.POINTER(vp)]),
     "tucker_truncate": (C.c_int32, [vp, vp, C.c_double, C.POINTER(vp), dp]),
     "tk_tpcg_defaults": (None, [C.POINTER(TpcgParams)]),
     "tk_sym_eig": (C.c_int32, [vp, vp, C.c_int32, vp, vp]),
@@ -377,15 +380,25 @@ class Preconditioner(_Handle):
 
 # --- the hot-path calls ----------------------------------------------------------------
 
-def tucker_apply_op(ctx, op: Operator, x: Tucker) -> Tucker:
+ARITH = {"f64": 0, "f32": 1}   # TK_ARITH_F64, TK_ARITH_F32
+ARITH_MIXED = 2                 # TK_ARITH_MIXED (tpcg_solve's precision rule)
+
+
+def tucker_apply_op(ctx, op: Operator, x: Tucker, arith: str = "f64") -> Tucker:
     h = vp()
-    ctx.check(lib().tucker_apply_op(ctx.h, op.h, x.h, C.byref(h)), "tucker_apply_op")
+    if arith == "f64":
+        ctx.check(lib().tucker_apply_op(ctx.h, op.h, x.h, C.byref(h)), "tucker_apply_op")
+    else:
+        ctx.check(lib().tucker_apply_op_arith(ctx.h, op.h, x.h, ARITH[arith], C.byref(h)), "tucker_apply_op_arith")
     return Tucker(ctx, h)
 
 
-def fd_precond(ctx, P: Preconditioner, s: Tucker) -> Tucker:
+def fd_precond(ctx, P: Preconditioner, s: Tucker, arith: str = "f64") -> Tucker:
     h = vp()
-    ctx.check(lib().fd_precond(ctx.h, P.h, s.h, C.byref(h)), "fd_precond")
+    if arith == "f64":
+        ctx.check(lib().fd_precond(ctx.h, P.h, s.h, C.byref(h)), "fd_precond")
+    else:
+        ctx.check(lib().fd_precond_arith(ctx.h, P.h, s.h, ARITH[arith], C.byref(h)), "fd_precond_arith")
     return Tucker(ctx, h)
 
 
@@ -447,7 +460,7 @@ def tpcg_solve_block(ctx, ops, precs, f, allow_noconv=False, **params):
         raise TkError(st, f"tpcg_solve_block: {msg.decode() if msg else ''}")
     return x, {"iters": info.iters, "converged": bool(info.converged), "relres": info.relres,
                "rank": tuple(info.rank), "eps_final": info.eps_final, "trel_calls": info.trel_calls,
-               "status": st}
+               "f32_applications": info.f32_applications, "status": st}
 
 
 def dgemm(ctx, ta: bool, tb: bool, M: int, N: int, K: int, alpha: float, A_dev, lda: int,
@@ -463,11 +476,16 @@ def dgemm(ctx, ta: bool, tb: bool, M: int, N: int, K: int, alpha: float, A_dev, 
 
 
 def tpcg_params(**kw) -> TpcgParams:
+    """Parameters of tpcg_solve; arith="mixed" selects the precision rule of
+    TK_ARITH_MIXED ("f64", the default, keeps every step in FP64)."""
     prm = TpcgParams()
     lib().tk_tpcg_defaults(C.byref(prm))
     for k, v in kw.items():
-        if v is not None:
-            setattr(prm, k, v)
+        if v is None:
+            continue
+        if k == "arith":
+            v = {"f64": ARITH["f64"], "mixed": ARITH_MIXED}[v] if isinstance(v, str) else v
+        setattr(prm, k, v)
     return prm
 
 
@@ -482,4 +500,4 @@ def tpcg_solve(ctx, op: Operator, P: Preconditioner, f: Tucker, allow_noconv=Fal
         raise TkError(st, f"tpcg_solve: {msg.decode() if msg else ''}")
     return x, {"iters": info.iters, "converged": bool(info.converged), "relres": info.relres,
                "rank": tuple(info.rank), "eps_final": info.eps_final, "trel_calls": info.trel_calls,
-               "status": st}
+               "f32_applications": info.f32_applications, "status": st}

@@ -35,17 +35,26 @@ def setup():
     return ctx, w, xr, lib
 
 
+@pytest.mark.parametrize("arith", ["f64", "mixed"])
 @pytest.mark.parametrize("tol,eps_min,bound", [(1e-6, 1e-8, 1e-5), (1e-7, 1e-9, 1e-6)])
-def test_tpcg_deformed_against_full_reference(setup, tol, eps_min, bound):
+def test_tpcg_deformed_against_full_reference(setup, tol, eps_min, bound, arith):
+    """arith = "mixed": the preconditioner and the operator products that steer
+    the search directions in FP32 arithmetic (TK_ARITH_MIXED); the bound
+    against the FP64 reference is the same, since the residual is recomputed
+    in FP64."""
     from paper_2306_00632_amd import tk
     ctx, w, xr, (op, P, f) = setup
-    say(f"tpcg deformed tol={tol} eps_min={eps_min}")
-    x, info = tk.tpcg_solve(ctx, op, P, f, tol=tol, eps_min=eps_min, maxit=300, verbose=1)
+    say(f"tpcg deformed tol={tol} eps_min={eps_min} arith={arith}")
+    x, info = tk.tpcg_solve(ctx, op, P, f, tol=tol, eps_min=eps_min, maxit=300, verbose=1, arith=arith)
     err = rel(to_oracle_plain(x).full(), xr)
     say(f"   iters={info['iters']} relres={info['relres']:.2e} rank={info['rank']} "
-        f"trel={info['trel_calls']} rel_err={err:.2e}")
+        f"trel={info['trel_calls']} f32={info['f32_applications']} rel_err={err:.2e}")
     assert info["converged"]
     assert err < bound
+    if arith == "mixed":
+        assert info["f32_applications"] > 0
+    else:
+        assert info["f32_applications"] == 0
 
 
 def test_tpcg_mid_size_matches_oracle_iterations():
