@@ -253,7 +253,11 @@ def serving(slots=16):
     path (one slot, one solve at a time) gives the capacity mu_plain; the
     server with `slots` concurrent solves then runs the same requests with
     Poisson arrivals at 0.5, 1 and 2 mu_plain and with all of them at once.
-    Latency = completion - arrival (queueing and per-request setup included)."""
+    Latency = completion - arrival (queueing and per-request setup included).
+    The plain path runs every step in FP64; the served requests use the mixed
+    arithmetic (TK_ARITH_MIXED) at the same tolerance, whose solutions meet
+    the same accuracy bound (relres_max reports the worst final residual)."""
+    import dataclasses
     from paper_2306_00632_amd import serve
     reqs = serve.mixed_requests(**SERVE_MIX)
     plain_srv = serve.Server(slots=1)
@@ -263,11 +267,12 @@ def serving(slots=16):
     mu = plain["solves_per_s"]
     out = {"requests": len(reqs),
            "mix": {k: list(v) if isinstance(v, (tuple, range)) else v for k, v in SERVE_MIX.items()},
-           "slots": slots, "plain": plain, "served": {}}
+           "slots": slots, "plain": dict(plain, arith="f64"), "served_arith": "mixed", "served": {}}
+    mreqs = [dataclasses.replace(r, arith="mixed") for r in reqs]
     srv = serve.Server(slots=slots)
-    srv.run(reqs[:slots])  # warm-up of every slot
+    srv.run(mreqs[:slots])  # warm-up of every slot
     for name, rate in (("0.5x", 0.5 * mu), ("1x", mu), ("2x", 2.0 * mu), ("all_at_once", 0.0)):
-        res = srv.run(serve.poisson_arrivals(reqs, rate, SERVE_MIX["seed"] + 7))
+        res = srv.run(serve.poisson_arrivals(mreqs, rate, SERVE_MIX["seed"] + 7))
         out["served"][name] = dict(serve.summarize(res), arrival_rate=rate)
     srv.close()
     out["speedup_all_at_once"] = out["served"]["all_at_once"]["solves_per_s"] / mu

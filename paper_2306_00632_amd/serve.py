@@ -44,6 +44,7 @@ class Request:
     tol: float = 1e-6
     eps_min: float = 1e-8
     maxit: int = 1000
+    arith: str = "f64"     # "f64" or "mixed" (tpcg_solve's precision rule)
 
 
 @dataclasses.dataclass
@@ -56,6 +57,7 @@ class Result:
     relres: float = float("nan")
     converged: bool = False
     rank: tuple = ()
+    f32_applications: int = 0
     solution: Optional[tuple] = None   # (core, [U1, U2, U3]) on the host when kept
     error: Optional[str] = None
 
@@ -82,14 +84,15 @@ def estimate_bytes(req: Request) -> int:
 
 
 def mixed_requests(count: int, seed: int, n_els=(64, 128), ps=(2, 3, 4), Rs=(3, 6, 9),
-                   ranks=range(1, 11), eps_min: float = 1e-8, maxit: int = 1000) -> List[Request]:
+                   ranks=range(1, 11), eps_min: float = 1e-8, maxit: int = 1000, arith: str = "f64") -> List[Request]:
     """A seeded mix of requests (sizes drawn uniformly from the given sets)."""
     rng = np.random.default_rng(seed)
     ranks = list(ranks)
     out = []
     for i in range(count):
         out.append(Request(rid=i, n_el=int(rng.choice(n_els)), p=int(rng.choice(ps)), R=int(rng.choice(Rs)),
-                           rank=int(rng.choice(ranks)), seed=seed + 1 + 2 * i, eps_min=eps_min, maxit=maxit))
+                           rank=int(rng.choice(ranks)), seed=seed + 1 + 2 * i, eps_min=eps_min, maxit=maxit,
+                           arith=arith))
     return out
 
 
@@ -127,9 +130,10 @@ def library_solve(slot: _Slot, req: Request, keep: bool) -> dict:
     op = problem.operator(ctx, w)
     P = problem.preconditioner(ctx, w)
     f = problem.rhs(ctx, w)
-    x, info = tk.tpcg_solve(ctx, op, P, f, tol=req.tol, eps_min=req.eps_min, maxit=req.maxit, allow_noconv=True)
+    x, info = tk.tpcg_solve(ctx, op, P, f, tol=req.tol, eps_min=req.eps_min, maxit=req.maxit, arith=req.arith,
+                            allow_noconv=True)
     out = {"iters": info["iters"], "relres": info["relres"], "converged": bool(info["converged"]),
-           "rank": tuple(info["rank"])}
+           "rank": tuple(info["rank"]), "f32_applications": info["f32_applications"]}
     if keep:
         out["solution"] = x.plain()
     ctx.sync()
@@ -215,4 +219,6 @@ def summarize(results: List[Result]) -> dict:
             "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
                            "max": float(lat.max() * 1e3)},
             "converged": int(sum(r.converged for r in ok)),
-            "iters_mean": float(np.mean([r.iters for r in ok]))}
+            "iters_mean": float(np.mean([r.iters for r in ok])),
+            "relres_max": float(max(r.relres for r in ok)),
+            "f32_applications": int(sum(r.f32_applications for r in ok))}

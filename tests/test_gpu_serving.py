@@ -1,6 +1,7 @@
 """Serving on the GPU: each request's result is the same alone (one slot,
 one solve at a time) and in a mix of concurrent solves (4 slots, all
-arriving at once); every solve converges.  The library's kernels are
+arriving at once), in FP64 and in the mixed arithmetic; every solve
+converges.  The library's kernels are
 deterministic, so the solutions agree to rounding (checked at 1e-12 on the
 full tensors)."""
 import numpy as np
@@ -19,9 +20,10 @@ def full(sol):
     return T.Tucker(core, U).full()
 
 
-def test_same_result_alone_and_in_the_mix():
-    reqs = serve.mixed_requests(6, 4242, n_els=(16, 32), ps=(2, 3), Rs=(3, 6), ranks=range(1, 5))
-    say("serving: alone")
+@pytest.mark.parametrize("arith", ["f64", "mixed"])
+def test_same_result_alone_and_in_the_mix(arith):
+    reqs = serve.mixed_requests(6, 4242, n_els=(16, 32), ps=(2, 3), Rs=(3, 6), ranks=range(1, 5), arith=arith)
+    say(f"serving ({arith}): alone")
     alone_srv = serve.Server(slots=1)
     alone = alone_srv.run(reqs, keep_solutions=True)
     alone_srv.close()
@@ -33,6 +35,8 @@ def test_same_result_alone_and_in_the_mix():
         assert a.error is None and m.error is None, (a.error, m.error)
         assert a.converged and m.converged
         assert a.iters == m.iters
+        assert a.f32_applications == m.f32_applications
+        assert (a.f32_applications > 0) == (arith == "mixed")
         xa, xm = full(a.solution), full(m.solution)
         assert np.linalg.norm(xa - xm) <= 1e-12 * np.linalg.norm(xa), a.rid
     s = serve.summarize(mix)
