@@ -23,7 +23,8 @@ namespace gpu {
 // wavefronts computes a (16 WM) x (16 NT) tile of C; wavefront w owns rows
 // [16w, 16w+16) and NT column tiles of 16, i.e. NT 16x16 accumulators.  K is
 // staged through LDS in steps of BK = 16 (double buffered: the next step's
-// global loads are in flight while the current step is multiplied).  The
+// global loads are in flight while the current step is multiplied; sub-steps
+// of 4 wholly past the end of K, all zero padding, are skipped).  The
 // tile leaves through LDS, 48 columns at a time, so every column of C is
 // written (and, with beta != 0, read) as one contiguous run of rows.
 // Operand layout of the instruction (lane l, element v): A[l%16][l/16],
@@ -123,6 +124,7 @@ __global__ __launch_bounds__(64 * WM) void k_dgemm(int M, int N, int K, double a
     if (more) load(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
+      if (k0 + ks >= kend) break;  // the rest of the step is zero padding (uniform)
       const double af = As[buf][ks + fk][fr];
 #pragma unroll
       for (int j = 0; j < NT; ++j) {

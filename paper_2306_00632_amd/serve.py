@@ -7,9 +7,11 @@ keeps `slots` solves in flight: each slot is a worker thread with its own
 HIP stream (default priority) and library context (its own stream-ordered
 memory pool), and a dispatcher admits waiting requests in arrival order as
 soon as a slot is free and the request's estimated device footprint fits
-the HBM budget.  A request builds its operator, preconditioner and
-right-hand side in its slot's context, solves, copies the solution's
-Tucker data to the host if asked, and releases its device memory.
+the HBM budget.  A request builds its operator and right-hand side in its
+slot's context, solves, copies the solution's Tucker data to the host if
+asked, and releases its device memory.  The FD preconditioner depends only
+on (n_el, p) (the parametric 1D matrices, the Appendix B data and the
+exponential sum), so each slot builds it once per pair and keeps it.
 
 HIP multiplexes the streams of a process onto GPU_MAX_HW_QUEUES hardware
 queues (4 by default); each slot drives three streams (its solve's main
@@ -110,15 +112,24 @@ def poisson_arrivals(requests: List[Request], rate: float, seed: int) -> List[Re
 
 
 class _Slot:
-    """A worker: one HIP stream and one library context."""
+    """A worker: one HIP stream, one library context and its preconditioners."""
 
     def __init__(self, device: int):
         import torch
         from . import tk
         self.stream = torch.cuda.Stream(device=device)   # default priority
         self.ctx = tk.Context(device, stream=self.stream.cuda_stream)
+        self.precs = {}   # (n_el, p) -> Preconditioner
+
+    def preconditioner(self, w):
+        from . import problem
+        key = (w.n_el, w.p)
+        if key not in self.precs:
+            self.precs[key] = problem.preconditioner(self.ctx, w)
+        return self.precs[key]
 
     def close(self):
+        self.precs.clear()
         self.ctx.close()
 
 
@@ -128,7 +139,7 @@ def library_solve(slot: _Slot, req: Request, keep: bool) -> dict:
     w = request_workload(req)
     ctx = slot.ctx
     op = problem.operator(ctx, w)
-    P = problem.preconditioner(ctx, w)
+    P = slot.preconditioner(w)
     f = problem.rhs(ctx, w)
     x, info = tk.tpcg_solve(ctx, op, P, f, tol=req.tol, eps_min=req.eps_min, maxit=req.maxit, arith=req.arith,
                             allow_noconv=True)
@@ -137,7 +148,7 @@ def library_solve(slot: _Slot, req: Request, keep: bool) -> dict:
     if keep:
         out["solution"] = x.plain()
     ctx.sync()
-    del x, op, P, f
+    del x, op, f
     return out
 
 
