@@ -105,25 +105,48 @@ def matrix_full(n_el: int, p: int, kind: str, weight=(1.0, 0.0, 0.0, 0.0),
     return Ba.T @ (wx[:, None] * Bb)
 
 
+def dof_range(n_el: int, p: int, bc=(0, 0)) -> tuple[int, int]:
+    """[lo, hi) of the full basis kept by the space with boundary flags
+    bc = (k0, k1) (Appendix B's notation: 1 = Neumann, 0 = Dirichlet at x = 0
+    and x = 1): a Dirichlet end drops the one basis function that does not
+    vanish there (Sec. 2.2), a Neumann end keeps it.  n = hi - lo =
+    n_el + p - 2 + k0 + k1."""
+    k0, k1 = bc
+    return (0 if k0 else 1), n_el + p - (0 if k1 else 1)
+
+
 def matrix(n_el: int, p: int, kind: str, weight=(1.0, 0.0, 0.0, 0.0),
-           nq: int | None = None) -> np.ndarray:
-    """The same integral restricted to the Dirichlet space of Sec. 2.2
-    (basis functions 2..m-1), n = n_el + p - 2."""
+           nq: int | None = None, bc=(0, 0)) -> np.ndarray:
+    """The same integral restricted to the space with boundary flags bc; the
+    default (0, 0) is the Dirichlet space of Sec. 2.2 (basis functions
+    2..m-1), n = n_el + p - 2."""
     A = matrix_full(n_el, p, kind, weight, nq)
-    return A[1:-1, 1:-1]
+    lo, hi = dof_range(n_el, p, bc)
+    return A[lo:hi, lo:hi]
 
 
-def load_vector(n_el: int, p: int, weight, nq: int | None = None) -> np.ndarray:
-    """F_i = int_0^1 b_i(x) g(x) dx for the Dirichlet basis (App. A, the 1D
-    moments forming the rhs factors), g from the weight family."""
+def load_vector(n_el: int, p: int, weight, nq: int | None = None, bc=(0, 0)) -> np.ndarray:
+    """F_i = int_0^1 b_i(x) g(x) dx for the basis of the space with boundary
+    flags bc (App. A, the 1D moments forming the rhs factors), g from the
+    weight family."""
     nq = p + 5 if nq is None else nq
     kn = open_knots(n_el, p)
     x, w = gauss_points(n_el, nq)
     B = basis(kn, p, x, 0)
     F = B.T @ (w * weight_values(weight, x))
-    return F[1:-1]
+    lo, hi = dof_range(n_el, p, bc)
+    return F[lo:hi]
 
 
 def dirichlet_basis_at(n_el: int, p: int, x, der: int = 0) -> np.ndarray:
     """Values/derivatives of the Dirichlet basis b_1..b_n at points x."""
     return basis(open_knots(n_el, p), p, x, der)[:, 1:-1]
+
+
+def greville(n_el: int, p: int) -> np.ndarray:
+    """Greville abscissae of the full basis, xi_i = (t_{i+1} + ... + t_{i+p})/p:
+    sum_i xi_i b_i(x) = x on [0, 1] (B-splines of degree p >= 1 reproduce
+    linear polynomials with these coefficients)."""
+    kn = open_knots(n_el, p)
+    m = n_el + p
+    return np.array([kn[i + 1:i + p + 1].mean() for i in range(m)])

@@ -93,13 +93,17 @@ def _constraints(n_el, p, at):
     return np.array(rows).reshape(-1, n)
 
 
-def exact_eig(n_el: int, p: int):
+def exact_eig(n_el: int, p: int, bc=(0, 0)):
     """(U, Lambda) of eq. factorizations for one direction: K U = M U Lambda,
-    U^T M U = I, with the parametric 1D stiffness and mass (Dirichlet space)."""
-    K = bspline.matrix(n_el, p, "stiff")
-    M = bspline.matrix(n_el, p, "mass")
+    U^T M U = I, with the parametric 1D stiffness and mass on the space with
+    boundary flags bc (default: the Dirichlet space).  With Neumann at both
+    ends the constants are in the space and the smallest eigenvalue is 0 in
+    exact arithmetic; computed values below 1e-12 lambda_max (rounding: the
+    smallest nonzero one is about pi^2) are set to 0."""
+    K = bspline.matrix(n_el, p, "stiff", bc=bc)
+    M = bspline.matrix(n_el, p, "mass", bc=bc)
     lam, U = sla.eigh(K, M)
-    return U, lam
+    return U, np.where(lam < 1e-12 * lam.max(), 0.0, lam)
 
 
 def approx_eig(n_el: int, p: int):
@@ -167,19 +171,24 @@ class LowRankFD:
     preconditioners with direction coefficients); `expsum_table` may hold
     precomputed (R_P, alpha, omega) for this M_P."""
 
-    def __init__(self, n_el, p, eps_prec=0.1, coef=(1.0, 1.0, 1.0), expsum_table=None, exact=False):
+    def __init__(self, n_el, p, eps_prec=0.1, coef=(1.0, 1.0, 1.0), expsum_table=None, exact=False,
+                 bcs=((0, 0), (0, 0), (0, 0))):
         self.Ut, self.lam = [], []
         if np.isscalar(n_el):
             n_el = (n_el,) * 3
         for i in range(3):
             if exact:   # Algorithm 4 with the exact factorizations of Algorithm 3
-                U, lam = exact_eig(n_el[i], p)
+                U, lam = exact_eig(n_el[i], p, bcs[i])
             else:
+                if tuple(bcs[i]) != (0, 0):
+                    raise NotImplementedError("the Appendix B approximation is built for Dirichlet ends only")
                 U, lam, _ = approx_eig(n_el[i], p)
             self.Ut.append(U)
             self.lam.append(coef[i] * lam)
         self.lam_min = sum(np.min(l) for l in self.lam)
         self.lam_max = sum(np.max(l) for l in self.lam)
+        if not self.lam_min > 0:
+            raise ValueError("the operator is singular (Neumann at every end of every direction)")
         self.M_P = self.lam_max / self.lam_min
         if expsum_table is None:
             R, al, om, E, Eprev = expsum.exp_sum_for(self.M_P, eps_prec)

@@ -1,0 +1,136 @@
+"""Pins of the oracle's boundary-condition support (oracle/bc.py, the bc
+flags of oracle/bspline.py and oracle/fd.py): Neumann ends of Appendix B
+and the non-homogeneous Dirichlet system of the remark closing Sec. 3.
+
+Each check is fixed by the mathematics, not by the oracle's own formulas:
+* with Neumann at both ends the constants are in the space, so the
+  stiffness matrix annihilates the vector of ones, and the mass matrix's
+  row sums are the basis integrals (t_{i+p+1} - t_i)/(p+1);
+* the low generalized eigenvalues of (K, M) converge to the continuous
+  Laplacian's, ((j - k0/2 - k1/2) pi)^2 (the closed form Appendix B uses
+  for its approximation), at the rate h^(2p) of spline eigenvalues;
+* the Greville abscissae reproduce x;
+* a linear function is in the spline space and harmonic, so the discrete
+  solution with its Dirichlet data, homogeneous Neumann data where its
+  normal derivative vanishes and f = 0 is the function itself, to
+  rounding: u = 1 + 3z with Dirichlet at z = 0, 1 and Neumann on the other
+  faces, and u = 1 with Dirichlet at z = 0 only;
+* the exact FD of Algorithm 3 on the BC spaces inverts the Laplacian.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bc as obc
+from oracle import bspline, fd
+from oracle.fullpcg import dense_solve
+from oracle.tucker import Tucker
+
+BCS = [(0, 0), (1, 1), (1, 0), (0, 1)]
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_neumann_stiffness_annihilates_constants(p):
+    rng = np.random.default_rng(p)
+    for _ in range(3):
+        wgt = (1.0, 0.5, *rng.uniform(0, 2, 2))
+        K = bspline.matrix(12, p, "stiff", wgt, bc=(1, 1))
+        assert K.shape == (12 + p, 12 + p)
+        assert np.abs(K @ np.ones(K.shape[0])).max() <= 1e-12 * np.abs(K).max()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5])
+def test_neumann_mass_row_sums_are_basis_integrals(p):
+    n_el = 9
+    M = bspline.matrix(n_el, p, "mass", bc=(1, 1))
+    t = bspline.open_knots(n_el, p)
+    ref = np.array([(t[i + p + 1] - t[i]) / (p + 1) for i in range(n_el + p)])
+    np.testing.assert_allclose(M.sum(axis=1), ref, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("p", [2, 3])
+def test_low_eigenvalues_match_the_continuous_laplacian(bc, p):
+    n_el = 64
+    K = bspline.matrix(n_el, p, "stiff", bc=bc)
+    M = bspline.matrix(n_el, p, "mass", bc=bc)
+    assert K.shape[0] == n_el + p - 2 + sum(bc)
+    lam = np.sort(np.linalg.eigvals(np.linalg.solve(M, K)).real)
+    shift = 0.5 * (bc[0] + bc[1])
+    for j in range(1, 4):
+        exact = ((j - shift) * np.pi) ** 2
+        if exact == 0.0:
+            assert abs(lam[j - 1]) <= 1e-9
+            continue
+        # spline eigenvalue error ~ (j pi h)^(2p) relative
+        assert abs(lam[j - 1] - exact) <= 10 * (j * np.pi / n_el) ** (2 * p) * exact, (j, lam[j - 1], exact)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_greville_reproduces_x(p):
+    n_el = 7
+    x = np.linspace(0.0, 1.0, 23)
+    B = bspline.basis(bspline.open_knots(n_el, p), p, x, 0)
+    np.testing.assert_allclose(B @ bspline.greville(n_el, p), x, atol=1e-14)
+    np.testing.assert_allclose(B.sum(axis=1), 1.0, atol=1e-14)
+
+
+def _dense_bc_solve(w, bcs, g, f=None):
+    op = obc.operator(w, bcs)
+    rhs = obc.lifted_rhs(w, bcs, g, f)
+    return dense_solve(op, rhs.full())
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_linear_solution_dirichlet_top_bottom_neumann_sides(p):
+    n_el = 5
+    w = W.laplace_cube(n_el, p)
+    bcs = ((1, 1), (1, 1), (0, 0))
+    g = obc.linear_coefficients(n_el, p, (1.0, 0.0, 0.0, 3.0))
+    x = _dense_bc_solve(w, bcs, g)
+    ref = obc.restrict(g, n_el, p, bcs).full()
+    assert x.shape == (n_el + p, n_el + p, n_el + p - 2)
+    assert np.abs(x - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_constant_solution_dirichlet_at_one_face(p):
+    n_el = 5
+    w = W.laplace_cube(n_el, p)
+    bcs = ((1, 1), (1, 1), (0, 1))
+    g = obc.linear_coefficients(n_el, p, (1.0, 0.0, 0.0, 0.0))
+    x = _dense_bc_solve(w, bcs, g)
+    assert np.abs(x - 1.0).max() <= 1e-11
+
+
+def test_lifting_vanishes_for_homogeneous_data_and_is_linear():
+    n_el, p = 5, 2
+    w = W.laplace_cube(n_el, p)
+    bcs = ((1, 0), (0, 0), (0, 1))
+    zero = Tucker(np.zeros((1, 1, 1)), [np.ones((n_el + p, 1))] * 3)
+    assert np.abs(obc.lifted_rhs(w, bcs, zero).full()).max() == 0.0
+    g1 = obc.linear_coefficients(n_el, p, (1.0, 2.0, 0.0, 0.0))
+    g2 = obc.linear_coefficients(n_el, p, (0.0, 0.0, -1.0, 0.5))
+    g12 = obc.linear_coefficients(n_el, p, (1.0, 2.0, -1.0, 0.5))
+    r = [obc.lifted_rhs(w, bcs, g).full() for g in (g1, g2, g12)]
+    np.testing.assert_allclose(r[0] + r[1], r[2], atol=1e-12 * np.abs(r[2]).max())
+
+
+@pytest.mark.parametrize("bcs", [((1, 1), (1, 1), (0, 0)), ((1, 0), (0, 1), (0, 0)), ((0, 0), (1, 1), (0, 1))])
+def test_exact_fd_inverts_the_laplacian_on_bc_spaces(bcs):
+    n_el, p = 6, 3
+    Ks = [bspline.matrix(n_el, p, "stiff", bc=b) for b in bcs]
+    Ms = [bspline.matrix(n_el, p, "mass", bc=b) for b in bcs]
+    P = fd.ExactFD(Ks, Ms)
+    rng = np.random.default_rng(3)
+    n = [k.shape[0] for k in Ks]
+    X = rng.standard_normal(n)
+    w = W.laplace_cube(n_el, p)
+    AX = obc.operator(w, bcs).dense() @ X.reshape(-1, order="F")
+    Y = P.apply_full(AX.reshape(n, order="F"))
+    assert np.abs(Y - X).max() <= 1e-9 * np.abs(X).max()
+
+
+def test_all_neumann_is_rejected():
+    with pytest.raises(ValueError):
+        fd.LowRankFD(6, 2, 0.1, exact=True, bcs=((1, 1),) * 3)
