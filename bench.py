@@ -29,6 +29,9 @@ Prints one JSON line (see the "metric" key) with:
   matrix_cores         the library's DGEMM at order 4096 (probe of the FP64
                        matrix-core rate it reaches) and the solve's GEMMs as
                        fractions of the 78.6 TFLOP/s spec and of that probe
+  boundary_conditions  solves with Neumann ends and non-homogeneous Dirichlet
+                       data at n_el = 128 (manufactured u = 1 + 3z: error;
+                       the deformed recipe: iterations, time)
   serving              a seeded mix of solves served with several concurrent
                        solves (one stream and library context each) against
                        the plain one-at-a-time path: solves/s and p50/p99
@@ -38,7 +41,7 @@ Prints one JSON line (see the "metric" key) with:
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload deformed|small]
                        [--fd approx|exact] [--arith f64|mixed] [--no-hbm] [--no-serve]
-                       [--serve-slots S] [--no-cpu-baseline]
+                       [--no-bc] [--serve-slots S] [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -208,6 +211,63 @@ def mode_products_hbm(ctx, reps=5):
     return out
 
 
+def boundary_conditions(ctx, reps=3):
+    """Solves with Neumann ends and non-homogeneous Dirichlet data (Appendix
+    B flags; the lifting of the remark closing Sec. 3) at n_el = 128, p = 3:
+    Dirichlet at z = 0 and z = 1, Neumann on the four other faces, the
+    exact-eigenvector FD on those spaces.  (1) the Laplacian with the data
+    of u = 1 + 3z and f = 0, whose discrete solution is u itself: relative
+    error of the TPCG solution; (2) the deformed recipe's 9 weighted terms
+    with rhs of rank 5 and Dirichlet data of rank 2 (seeded): iterations and
+    time.  Times include the lifting (one operator product on the full
+    basis and a row restriction) and exclude the setup."""
+    import numpy as np
+    import torch
+    from paper_2306_00632_amd import problem, tk
+    import workloads as W
+    n_el, p = 128, 3
+    bcs = ((1, 1), (1, 1), (0, 0))
+    out = {"n_el": n_el, "p": p, "flags": [list(b) for b in bcs]}
+    w = W.laplace_cube(n_el, p)
+    gcore, gU = W.linear_dirichlet_data(n_el, p, (1.0, 0.0, 0.0, 3.0))
+    op, P = problem.operator_bc(ctx, w, bcs), problem.preconditioner_bc(ctx, w, bcs)
+    opf = problem.operator_bc(ctx, w, ((1, 1),) * 3)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = problem.lifted_rhs(ctx, w, bcs, gcore, gU, op_full=opf)
+        x, info = tk.tpcg_solve(ctx, op, P, f, tol=1e-8)
+        ctx.sync()
+        ts.append(time.perf_counter() - t0)
+    # the exact discrete solution: the data's coefficients at the unknowns
+    rng = [problem.dof_range(n_el, p, b) for b in bcs]
+    ref = np.einsum("abc,ia,jb,kc->ijk", gcore, *[gU[k][rng[k][0]:rng[k][1]] for k in range(3)])
+    core, U = x.plain()
+    xf = np.einsum("abc,ia,jb,kc->ijk", core, U[0], U[1], U[2])
+    out["manufactured"] = {"u": "1 + 3z", "tol": 1e-8, "iters": info["iters"], "rank": list(info["rank"]),
+                           "rel_err": float(np.linalg.norm(xf - ref) / np.linalg.norm(ref)),
+                           "ms_per_solve": 1e3 * min(ts)}
+    wd = W.weighted_cp(n_el, p, 9, 5, 2002, 2003)
+    n = [n_el + p - 2 + sum(b) for b in bcs]
+    fc, fU = W.random_tucker(n, (5, 5, 5), 2003)
+    gc, gU = W.random_tucker(n_el + p, (2, 2, 2), 2004)
+    op, P = problem.operator_bc(ctx, wd, bcs), problem.preconditioner_bc(ctx, wd, bcs)
+    opf = problem.operator_bc(ctx, wd, ((1, 1),) * 3)
+    fd = tk.Tucker.from_host(ctx, fc, fU)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = problem.lifted_rhs(ctx, wd, bcs, gc, gU, f=fd, op_full=opf)
+        x, info = tk.tpcg_solve(ctx, op, P, f, tol=1e-6, eps_min=1e-8)
+        ctx.sync()
+        ts.append(time.perf_counter() - t0)
+    out["deformed"] = {"tol": 1e-6, "iters": info["iters"], "relres": info["relres"], "rank": list(info["rank"]),
+                       "ms_per_solve": 1e3 * min(ts), "solves_per_s": 1.0 / min(ts)}
+    return out
+
+
 def matrix_cores(ctx, solve_kernels, reps=5):
     """FP64 matrix-core rates: a square GEMM of order 4096 through the
     library's own DGEMM (tk_dgemm, the kernel of every dense contraction of
@@ -319,6 +379,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm", action="store_true", help="skip the batched mode-product bandwidth runs and the DGEMM probe")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
+    ap.add_argument("--no-bc", action="store_true",
+                    help="skip the solves with Neumann ends and non-homogeneous Dirichlet data")
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--fd", choices=("approx", "exact"), default="approx",
                     help="preconditioner eigenpairs: Appendix B approximations applied by sine transforms "
@@ -439,6 +501,8 @@ def main():
     if not args.no_hbm:
         out["mode_products_hbm"] = mode_products_hbm(ctx)
         out["matrix_cores"] = matrix_cores(ctx, kernels)
+    if not args.no_bc:
+        out["boundary_conditions"] = boundary_conditions(ctx)
     if not args.no_serve:
         out["serving"] = serving(args.serve_slots)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:

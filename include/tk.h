@@ -80,6 +80,16 @@ tk_status tk_ctx_trim(tk_ctx* ctx);
  * EINVAL if p < 1, n_el < 1 or kind is unknown. */
 tk_status tk_assemble_1d(int32_t n_el, int32_t p, int32_t kind, const double weight[4], double* band);
 
+/* tk_assemble_1d on the space with boundary flags (k0, k1) of Appendix B:
+ * 1 = Neumann (the basis function that does not vanish at that end is
+ * kept), 0 = Dirichlet (it is dropped, Sec. 2.2); n = n_el + p - 2 + k0 + k1
+ * and (0, 0) is tk_assemble_1d.  With (1, 1) (every basis function) the
+ * matrices of the full space, used for the lifting of non-homogeneous
+ * Dirichlet data (remark closing Sec. 3, eq. nonhomog-dirichlet-system).
+ * EINVAL as tk_assemble_1d or if a flag is not 0 or 1. */
+tk_status tk_assemble_1d_bc(int32_t n_el, int32_t p, int32_t kind, const double weight[4], int32_t k0,
+                            int32_t k1, double* band);
+
 /* Load vector F_i = int b_i(x) w(x) dx (host, caller-owned, n doubles). */
 tk_status tk_load_vector_1d(int32_t n_el, int32_t p, const double weight[4], double* F);
 
@@ -126,6 +136,14 @@ tk_status tk_tucker_read(tk_ctx* ctx, const tk_tucker* t, int32_t k, double* U, 
 
 /* <x, y> (Sec. 2.3 scalar product; lazy sums expanded bilinearly). Syncs. */
 tk_status tk_tucker_dot(tk_ctx* ctx, const tk_tucker* x, const tk_tucker* y, double* out);
+
+/* Rows [off[k], off[k] + n[k]) of every mode-k factor of t (device copies;
+ * the cores are shared): the restriction of a tensor on a larger basis to a
+ * contiguous index range per direction, e.g. from the full spline basis to
+ * the unknowns of the spaces of tk_assemble_1d_bc.  EINVAL on a range outside
+ * t or an empty one.  Asynchronous. */
+tk_status tk_tucker_rows(tk_ctx* ctx, const tk_tucker* t, const int64_t off[3], const int64_t n[3],
+                         tk_tucker** out);
 
 /* Lazy a*x + b*y (Sec. 2.3 sum: factors concatenated, block-diagonal core). */
 tk_status tk_tucker_axpby(tk_ctx* ctx, double a, const tk_tucker* x, double b,
@@ -185,6 +203,16 @@ tk_status fd_setup(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_pre
  * arguments, ENUMERIC if an eigenvalue is not positive. */
 tk_status fd_setup_exact(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec,
                          const double coef[3], tk_prec** out, int32_t* R_P);
+
+/* fd_setup_exact on the spaces with boundary flags bc[2k] (x = 0) and
+ * bc[2k+1] (x = 1) of direction k (Appendix B's k0, k1: 1 Neumann, 0
+ * Dirichlet; n_k = n_el[k] + p - 2 + k0 + k1).  A direction with Neumann at
+ * both ends has the eigenvalue 0 (the constants; computed values below
+ * 1e-12 lambda_max are set to 0); the operator stays SPD as long as one
+ * direction has a Dirichlet end, else EINVAL.  EINVAL also for flags other
+ * than 0 and 1; the rest as fd_setup_exact. */
+tk_status fd_setup_exact_bc(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec,
+                            const double coef[3], const int32_t bc[6], tk_prec** out, int32_t* R_P);
 void tk_prec_free(tk_prec* P);
 
 /* R_P, lambda_min, lambda_max, E_{R_P}(M_P); alpha/omega (R_P doubles each,

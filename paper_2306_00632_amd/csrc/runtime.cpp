@@ -1199,6 +1199,18 @@ tk_status tk_assemble_1d(int32_t n_el, int32_t p, int32_t kind, const double wei
   return TK_OK;
 }
 
+tk_status tk_assemble_1d_bc(int32_t n_el, int32_t p, int32_t kind, const double weight[4], int32_t k0, int32_t k1,
+                            double* band) {
+  if (n_el < 1 || p < 1 || kind < 0 || kind > 3 || !weight || !band) return TK_EINVAL;
+  if ((k0 != 0 && k0 != 1) || (k1 != 0 && k1 != 1) || n_el + p - 2 + k0 + k1 < 1) return TK_EINVAL;
+  try {
+    assemble_band(n_el, p, kind, weight, band, k0, k1);
+  } catch (...) {
+    return TK_ENOMEM;
+  }
+  return TK_OK;
+}
+
 tk_status tk_load_vector_1d(int32_t n_el, int32_t p, const double weight[4], double* F) {
   if (n_el < 1 || p < 1 || !weight || !F || n_el + p - 2 < 1) return TK_EINVAL;
   try {
@@ -1336,6 +1348,28 @@ tk_status tk_tucker_axpby(tk_ctx* ctx, double a, const tk_tucker* x, double b, c
   if (!ctx || !x || !y || !out) return TK_EINVAL;
   *out = nullptr;
   return guarded(ctx, [&]() { *out = lin_comb(ctx, a, x, b, y); return TK_OK; });
+}
+
+tk_status tk_tucker_rows(tk_ctx* ctx, const tk_tucker* t, const int64_t off[3], const int64_t n[3],
+                         tk_tucker** out) {
+  if (!ctx || !t || !off || !n || !out) return TK_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (off[k] < 0 || n[k] < 1 || off[k] + n[k] > t->n[k]) return TK_EINVAL;
+  *out = nullptr;
+  return guarded(ctx, [&]() {
+    auto* r = new tk_tucker;
+    for (int k = 0; k < 3; ++k) {
+      r->n[k] = int(n[k]);
+      r->m[k] = t->m[k];
+      r->U[k] = alloc(ctx, (size_t)r->n[k] * r->m[k]);
+      if (r->m[k] > 0)
+        HIPCHK(hipMemcpy2DAsync(r->U[k]->p, sizeof(double) * r->n[k], t->U[k]->p + off[k], sizeof(double) * t->n[k],
+                                sizeof(double) * r->n[k], r->m[k], hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    r->blocks = t->blocks;  // cores are immutable and shared
+    *out = r;
+    return TK_OK;
+  });
 }
 
 tk_status tk_op_create(tk_ctx* ctx, int32_t p, const int64_t n[3], const int32_t nmat[3],
@@ -1524,8 +1558,10 @@ tk_status fd_setup(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_pre
   });
 }
 
-tk_status fd_setup_exact(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec, const double coef[3],
-                         tk_prec** out, int32_t* R_P) {
+// fd_setup_exact on the spaces with boundary flags bc[2k], bc[2k+1] (null:
+// Dirichlet everywhere)
+static tk_status setup_exact(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec, const double coef[3],
+                             const int32_t* bc, tk_prec** out, int32_t* R_P) {
   if (!ctx || !n_el || !out || !(eps_prec > 0.0)) return TK_EINVAL;
   *out = nullptr;
   return guarded(ctx, [&]() {
@@ -1538,7 +1574,8 @@ tk_status fd_setup_exact(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double e
       if (!(c > 0.0)) throw Error(TK_EINVAL, "fd_setup_exact: direction coefficients must be positive");
       std::vector<double> C;
       int n = 0;
-      if (!fd_exact_pencil(n_el[k], p, c, C, L[k], n, msg)) throw Error(TK_EINVAL, msg);
+      const int k0 = bc ? bc[2 * k] : 0, k1 = bc ? bc[2 * k + 1] : 0;
+      if (!fd_exact_pencil(n_el[k], p, c, C, L[k], n, msg, k0, k1)) throw Error(TK_EINVAL, msg);
       P->n_exact[k] = n;
       // eigenpairs of C with the library's symmetric eigensolver
       BufP Cd = alloc(ctx, (size_t)n * n), V = alloc(ctx, (size_t)n * n), w = alloc(ctx, (size_t)n);
@@ -1547,8 +1584,15 @@ tk_status fd_setup_exact(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double e
       gpu::sym_eig(ctx->stream, Cd->p, n, V->p, w->p, work->p);
       std::vector<double> Q = d2h(ctx, V->p, (size_t)n * n);
       P->lam_exact[k] = d2h(ctx, w->p, (size_t)n);
-      for (double v : P->lam_exact[k])
-        if (!(v > 0.0)) throw Error(TK_ENUMERIC, "fd_setup_exact: non-positive eigenvalue");
+      // with Neumann at both ends the constants give a zero eigenvalue;
+      // computed values below 1e-12 lambda_max are rounding (the smallest
+      // nonzero one is about pi^2 coef) and are set to 0
+      auto& lk = P->lam_exact[k];
+      const double lmax = *std::max_element(lk.begin(), lk.end());
+      for (double& v : lk) {
+        if (!std::isfinite(v) || v < -1e-8 * std::fabs(lmax)) throw Error(TK_ENUMERIC, "fd_setup_exact: negative eigenvalue");
+        if (v < 1e-12 * lmax) v = 0.0;
+      }
       fd_exact_vectors(L[k], n, p, Q.data());  // U = L^{-T} Q, M-orthonormal
       P->Ud[k] = alloc(ctx, (size_t)n * n);
       h2d(ctx, P->Ud[k]->p, Q.data(), (size_t)n * n);
@@ -1556,6 +1600,8 @@ tk_status fd_setup_exact(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double e
       P->lam_min += *std::min_element(l.begin(), l.end());
       P->lam_max += *std::max_element(l.begin(), l.end());
     }
+    if (!(P->lam_min > 0.0))
+      throw Error(TK_EINVAL, "fd_setup_exact: singular operator (Neumann at both ends of every direction)");
     ExpSum es;
     if (!expsum_for(P->lam_max / P->lam_min, eps_prec, es, msg)) throw Error(TK_ENUMERIC, msg);
     P->R = es.R;
@@ -1575,6 +1621,19 @@ tk_status fd_setup_exact(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double e
     *out = P.release();
     return TK_OK;
   });
+}
+
+tk_status fd_setup_exact(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec, const double coef[3],
+                         tk_prec** out, int32_t* R_P) {
+  return setup_exact(ctx, n_el, p, eps_prec, coef, nullptr, out, R_P);
+}
+
+tk_status fd_setup_exact_bc(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec, const double coef[3],
+                            const int32_t bc[6], tk_prec** out, int32_t* R_P) {
+  if (!bc) return TK_EINVAL;
+  for (int i = 0; i < 6; ++i)
+    if (bc[i] != 0 && bc[i] != 1) return TK_EINVAL;
+  return setup_exact(ctx, n_el, p, eps_prec, coef, bc, out, R_P);
 }
 
 void tk_prec_free(tk_prec* P) { delete P; }

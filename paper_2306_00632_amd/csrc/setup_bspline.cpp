@@ -127,8 +127,9 @@ static inline double weight_at(const double w[4], double x) {
   return w[0] + w[1] * std::cos(w[2] * x + w[3]);
 }
 
-void assemble_band(int n_el, int p, int kind, const double weight[4], double* band) {
-  const int n = n_el + p - 2;
+void assemble_band(int n_el, int p, int kind, const double weight[4], double* band, int k0, int k1) {
+  const int n = n_el + p - 2 + k0 + k1;
+  const int sh = 1 - k0;  // full-basis index of space index 0
   const int nb = 2 * p + 1;
   std::memset(band, 0, sizeof(double) * nb * n);
   const auto kn = open_knots(n_el, p);
@@ -146,11 +147,11 @@ void assemble_band(int n_el, int p, int kind, const double weight[4], double* ba
       const double wq = 0.5 * h * gw[q] * weight_at(weight, x);
       span_basis(kn, p, span, x, 1, vals.data());
       for (int a = 0; a <= p; ++a) {
-        const int i = span - p + a - 1;  // Dirichlet index (full index - 1)
+        const int i = span - p + a - sh;  // space index (full index - sh)
         if (i < 0 || i >= n) continue;
         const double va = vals[da * (p + 1) + a];
         for (int b = 0; b <= p; ++b) {
-          const int j = span - p + b - 1;
+          const int j = span - p + b - sh;
           if (j < 0 || j >= n) continue;
           const int o = j - i;
           band[(o + p) * n + i] += wq * va * vals[db * (p + 1) + b];

@@ -436,16 +436,20 @@ bool fd_direction_setup(int n_el, int p, double coef, FdDirection& d, std::strin
 // ---------------------------------------------------------------------------
 
 bool fd_exact_pencil(int n_el, int p, double coef, std::vector<double>& C, std::vector<double>& L, int& n,
-                     std::string& msg) {
+                     std::string& msg, int k0, int k1) {
   if (p < 1 || n_el <= p || n_el > 4096) {
     msg = "fd_setup_exact: need p >= 1 and p < n_el <= 4096";
     return false;
   }
-  n = n_el + p - 2;
+  if ((k0 != 0 && k0 != 1) || (k1 != 0 && k1 != 1)) {
+    msg = "fd_setup_exact: boundary flags must be 0 (Dirichlet) or 1 (Neumann)";
+    return false;
+  }
+  n = n_el + p - 2 + k0 + k1;
   const double unit[4] = {1.0, 0.0, 0.0, 0.0};
   std::vector<double> Mb(size_t(2 * p + 1) * n), Kb(size_t(2 * p + 1) * n);
-  assemble_band(n_el, p, 0, unit, Mb.data());
-  assemble_band(n_el, p, 1, unit, Kb.data());
+  assemble_band(n_el, p, 0, unit, Mb.data(), k0, k1);
+  assemble_band(n_el, p, 1, unit, Kb.data(), k0, k1);
   if (!band_cholesky(Mb, n, p, L)) {
     msg = "fd_setup_exact: mass matrix not positive definite";
     return false;

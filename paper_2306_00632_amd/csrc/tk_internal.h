@@ -31,10 +31,12 @@ int find_span(const std::vector<double>& knots, int p, double x);
 // Gauss-Legendre nodes/weights on [-1, 1].
 void gauss_legendre(int nq, std::vector<double>& x, std::vector<double>& w);
 
-// Dirichlet-space banded matrix int delta_a(b_i) delta_b(b_j) w dx with
-// w(x) = c0 + c1 cos(a x + b); DIA layout band[(o+p)*n + i] = A[i, i+o].
+// Banded matrix int delta_a(b_i) delta_b(b_j) w dx with w(x) = c0 + c1 cos(a x + b)
+// on the space with boundary flags (k0, k1) (1 = Neumann: the end basis
+// function is kept; 0 = Dirichlet: it is dropped), n = n_el + p - 2 + k0 + k1;
+// the default is the Dirichlet space.  DIA layout band[(o+p)*n + i] = A[i, i+o].
 // kind: 0 mass, 1 stiffness, 2 mixed (d/dx on test function i), 3 mixed (trial j).
-void assemble_band(int n_el, int p, int kind, const double weight[4], double* band);
+void assemble_band(int n_el, int p, int kind, const double weight[4], double* band, int k0 = 0, int k1 = 0);
 
 // Dirichlet-space load vector F_i = int b_i g dx, g from the weight family.
 void load_vector(int n_el, int p, const double weight[4], double* F);
@@ -77,13 +79,14 @@ struct FdDirection {
 
 bool fd_direction_setup(int n_el, int p, double coef, FdDirection& d, std::string& msg);
 
-// Exact generalized eigenpairs of (coef K, M) on the Dirichlet space, eq.
+// Exact generalized eigenpairs of (coef K, M) on the space with boundary
+// flags (k0, k1) (default: the Dirichlet space), eq.
 // (factorizations): with the banded Cholesky factor M = L L^T (L in the band
 // layout of band_cholesky), C = L^{-1} (coef K) L^{-T} (n x n, column-major,
 // symmetrized) has the same eigenvalues, and U = L^{-T} Q for its orthonormal
 // eigenvectors Q is M-orthonormal.
 bool fd_exact_pencil(int n_el, int p, double coef, std::vector<double>& C, std::vector<double>& L, int& n,
-                     std::string& msg);
+                     std::string& msg, int k0 = 0, int k1 = 0);
 // Q (n x n, column-major) <- L^{-T} Q
 void fd_exact_vectors(const std::vector<double>& L, int n, int p, double* Q);
 

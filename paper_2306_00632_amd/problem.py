@@ -32,6 +32,53 @@ def preconditioner(ctx, w, eps_prec=0.1, coef=(1.0, 1.0, 1.0), exact=False) -> t
     return tk.Preconditioner.create(ctx, w.n_el, w.p, eps_prec, coef, exact=exact)
 
 
+# --- boundary conditions other than homogeneous Dirichlet ---------------------
+
+def dof_range(n_el: int, p: int, bc) -> tuple:
+    """[lo, hi) of the full spline basis (n_el + p functions) kept by the space
+    with boundary flags bc = (k0, k1): 1 Neumann (kept end function), 0
+    Dirichlet (dropped)."""
+    return (0 if bc[0] else 1), n_el + p - (0 if bc[1] else 1)
+
+
+def operator_bc(ctx, w, bcs) -> tk.Operator:
+    """The workload's Tucker matrix on the spaces with flags bcs[k]
+    (bcs = ((1, 1),) * 3: the full basis)."""
+    bands = [np.stack([tk.assemble_1d_bc(w.n_el, w.p, kind, weight, bcs[k]) for kind, weight in w.modes[k]])
+             for k in range(3)]
+    n = [w.n_el + w.p - 2 + bcs[k][0] + bcs[k][1] for k in range(3)]
+    return tk.Operator.create(ctx, w.p, n, bands, w.nnz)
+
+
+def preconditioner_bc(ctx, w, bcs, eps_prec=0.1, coef=(1.0, 1.0, 1.0)) -> tk.Preconditioner:
+    """Exact-eigenvector FD (Algorithm 4 with Algorithm 3's factorizations) on
+    the spaces with flags bcs[k]."""
+    return tk.Preconditioner.create(ctx, w.n_el, w.p, eps_prec, coef, exact=True, bcs=bcs)
+
+
+def lifted_rhs(ctx, w, bcs, g_core, g_factors, f=None, op_full=None) -> tk.Tucker:
+    """f - A_dOmega g~ of the non-homogeneous Dirichlet system (remark closing
+    Sec. 3): g~ (Tucker: g_core, full-basis factors g_factors, n_el + p rows)
+    extends the Dirichlet data; g_B = g~ minus its restriction to the
+    unknowns (zero-extended), and A_dOmega g~ = R A_full g_B with the
+    full-basis operator and R the restriction of factor rows to the unknowns.
+    f (a tensor on the unknowns) may be None for f = 0."""
+    rng = [dof_range(w.n_el, w.p, bcs[k]) for k in range(3)]
+    masked = []
+    for k in range(3):
+        u = np.array(g_factors[k], dtype=np.float64, copy=True)
+        u[:rng[k][0]] = 0.0
+        u[rng[k][1]:] = 0.0
+        masked.append(u)
+    g = tk.Tucker.from_host(ctx, g_core, g_factors)
+    gm = tk.Tucker.from_host(ctx, g_core, masked)
+    neg_gb = tk.axpby(ctx, -1.0, g, 1.0, gm)   # -g_B
+    op_full = op_full or operator_bc(ctx, w, ((1, 1),) * 3)
+    lift = tk.tucker_rows(ctx, tk.tucker_apply_op(ctx, op_full, neg_gb), [r[0] for r in rng],
+                          [r[1] - r[0] for r in rng])   # -R A_full g_B
+    return lift if f is None else tk.axpby(ctx, 1.0, f, 1.0, lift)
+
+
 # --- block (3-component) systems --------------------------------------------
 
 def block_operator(ctx, bw) -> list:

@@ -52,6 +52,7 @@ EXPORTS = {
     "tk_ctx_sync": (C.c_int32, [vp]),
     "tk_ctx_trim": (C.c_int32, [vp]),
     "tk_assemble_1d": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, dp, dp]),
+    "tk_assemble_1d_bc": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, C.c_int32, dp]),
     "tk_load_vector_1d": (C.c_int32, [C.c_int32, C.c_int32, dp, dp]),
     "tk_fd_direction_host": (C.c_int32, [C.c_int32, C.c_int32, C.c_double, i32p, i32p, i32p, dp, dp, dp, dp]),
     "tk_expsum_host": (C.c_int32, [C.c_double, C.c_double, i32p, dp, dp, dp, dp]),
@@ -62,6 +63,7 @@ EXPORTS = {
     "tk_tucker_read": (C.c_int32, [vp, vp, C.c_int32, vp, C.c_int32, vp, C.c_int32]),
     "tk_tucker_dot": (C.c_int32, [vp, vp, vp, dp]),
     "tk_tucker_axpby": (C.c_int32, [vp, C.c_double, vp, C.c_double, vp, C.POINTER(vp)]),
+    "tk_tucker_rows": (C.c_int32, [vp, vp, i64p, i64p, C.POINTER(vp)]),
     "tk_op_create": (C.c_int32, [vp, C.c_int32, i64p, i32p, C.POINTER(dp), C.POINTER(CoreNz),
                                  C.c_int64, C.POINTER(vp)]),
     "tk_op_free": (None, [vp]),
@@ -69,6 +71,7 @@ EXPORTS = {
     "tucker_apply_op_arith": (C.c_int32, [vp, vp, vp, C.c_int32, C.POINTER(vp)]),
     "fd_setup": (C.c_int32, [vp, i32p, C.c_int32, C.c_double, dp, C.POINTER(vp), i32p]),
     "fd_setup_exact": (C.c_int32, [vp, i32p, C.c_int32, C.c_double, dp, C.POINTER(vp), i32p]),
+    "fd_setup_exact_bc": (C.c_int32, [vp, i32p, C.c_int32, C.c_double, dp, i32p, C.POINTER(vp), i32p]),
     "tk_prec_free": (None, [vp]),
     "tk_prec_info": (C.c_int32, [vp, i32p, dp, dp, dp, dp, dp]),
     "tk_prec_direction": (C.c_int32, [vp, C.c_int32, i32p, i32p, i32p, dp, dp, dp, dp]),
@@ -123,6 +126,18 @@ def assemble_1d(n_el: int, p: int, kind: str, weight=(1.0, 0.0, 0.0, 0.0)) -> np
     st = lib().tk_assemble_1d(n_el, p, KINDS[kind], _ptr(w), _ptr(band))
     if st != TK_OK:
         raise TkError(st, "tk_assemble_1d")
+    return band
+
+
+def assemble_1d_bc(n_el: int, p: int, kind: str, weight=(1.0, 0.0, 0.0, 0.0), bc=(0, 0)) -> np.ndarray:
+    """DIA band (2p+1, n) on the space with boundary flags bc = (k0, k1)
+    (1 Neumann, 0 Dirichlet), n = n_el + p - 2 + k0 + k1."""
+    n = n_el + p - 2 + bc[0] + bc[1]
+    band = np.zeros((2 * p + 1, n))
+    w = np.asarray(weight, dtype=np.float64)
+    st = lib().tk_assemble_1d_bc(n_el, p, KINDS[kind], _ptr(w), int(bc[0]), int(bc[1]), _ptr(band))
+    if st != TK_OK:
+        raise TkError(st, "tk_assemble_1d_bc")
     return band
 
 
@@ -345,13 +360,21 @@ class Preconditioner(_Handle):
     _free = "tk_prec_free"
 
     @classmethod
-    def create(cls, ctx, n_el, p, eps_prec=0.1, coef=(1.0, 1.0, 1.0), exact=False) -> "Preconditioner":
+    def create(cls, ctx, n_el, p, eps_prec=0.1, coef=(1.0, 1.0, 1.0), exact=False, bcs=None) -> "Preconditioner":
         """Appendix B eigen-approximations (fd_setup), or with exact=True the
-        exact generalized eigenpairs applied as dense GEMMs (fd_setup_exact)."""
+        exact generalized eigenpairs applied as dense GEMMs (fd_setup_exact);
+        bcs = ((k0, k1),) * 3 boundary flags (exact only: fd_setup_exact_bc)."""
         ne = (C.c_int32 * 3)(*((n_el,) * 3 if np.isscalar(n_el) else n_el))
         cf = np.asarray(coef, dtype=np.float64)
         h = vp()
         R = C.c_int32()
+        if bcs is not None:
+            if not exact:
+                raise ValueError("boundary flags need the exact-eigenvector preconditioner")
+            flags = (C.c_int32 * 6)(*[int(f) for b in bcs for f in b])
+            ctx.check(lib().fd_setup_exact_bc(ctx.h, ne, p, eps_prec, _ptr(cf), flags, C.byref(h), C.byref(R)),
+                      "fd_setup_exact_bc")
+            return cls(ctx, h)
         name = "fd_setup_exact" if exact else "fd_setup"
         ctx.check(getattr(lib(), name)(ctx.h, ne, p, eps_prec, _ptr(cf), C.byref(h), C.byref(R)), name)
         return cls(ctx, h)
@@ -413,6 +436,14 @@ def dot(ctx, x: Tucker, y: Tucker) -> float:
     out = C.c_double()
     ctx.check(lib().tk_tucker_dot(ctx.h, x.h, y.h, C.byref(out)), "tk_tucker_dot")
     return out.value
+
+
+def tucker_rows(ctx, t: Tucker, off, n) -> Tucker:
+    """Rows [off[k], off[k] + n[k]) of every mode-k factor (cores shared)."""
+    h = vp()
+    ctx.check(lib().tk_tucker_rows(ctx.h, t.h, (C.c_int64 * 3)(*off), (C.c_int64 * 3)(*n), C.byref(h)),
+              "tk_tucker_rows")
+    return Tucker(ctx, h)
 
 
 def axpby(ctx, a, x: Tucker, b, y: Tucker) -> Tucker:

@@ -108,3 +108,33 @@ def test_expsum_matches_oracle(tk, M):
     np.testing.assert_allclose(d["alpha"], al, rtol=1e-8)
     np.testing.assert_allclose(d["omega"], om, rtol=1e-8)
     assert d["err"] <= 0.1 / M < d["err_prev"]
+
+
+# --- 1D matrices on the spaces with Neumann/Dirichlet flags (Appendix B) ---------
+
+BCS = [(0, 0), (1, 1), (1, 0), (0, 1)]
+
+
+def band_dense(b, p):
+    n = b.shape[1]
+    A = np.zeros((n, n))
+    for o in range(-p, p + 1):
+        for i in range(n):
+            if 0 <= i + o < n:
+                A[i, i + o] = b[o + p, i]
+    return A
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("p", [1, 2, 3, 5])
+def test_assemble_1d_bc(bc, p):
+    """tk_assemble_1d_bc against the oracle's matrices on the same spaces
+    (elementwise 1e-13)."""
+    from oracle import bspline
+    from paper_2306_00632_amd import tk
+    for kind in ("mass", "stiff", "mixed10", "mixed01"):
+        wgt = (1.0, 0.5, 1.3, 0.2)
+        A = band_dense(tk.assemble_1d_bc(11, p, kind, wgt, bc), p)
+        ref = bspline.matrix(11, p, kind, wgt, bc=bc)
+        assert A.shape == ref.shape
+        assert np.abs(A - ref).max() <= 1e-13 * np.abs(ref).max(), kind

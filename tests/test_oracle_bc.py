@@ -134,3 +134,12 @@ def test_exact_fd_inverts_the_laplacian_on_bc_spaces(bcs):
 def test_all_neumann_is_rejected():
     with pytest.raises(ValueError):
         fd.LowRankFD(6, 2, 0.1, exact=True, bcs=((1, 1),) * 3)
+
+
+def test_workload_linear_data_matches_the_oracle():
+    """The input generator of the manufactured runs (workloads) against the
+    oracle's construction from its own knot vector and Greville abscissae."""
+    for n_el, p in ((5, 2), (16, 3), (9, 5)):
+        core, U = W.linear_dirichlet_data(n_el, p, (1.0, -2.0, 0.5, 3.0))
+        ref = obc.linear_coefficients(n_el, p, (1.0, -2.0, 0.5, 3.0))
+        np.testing.assert_allclose(Tucker(core, U).full(), ref.full(), rtol=0, atol=1e-14)

@@ -81,6 +81,21 @@ def weighted_cp(n_el: int, p: int, R: int, rank: int, seed_op: int,
                     modes, nnz, random_rhs(n_el + p - 2, rank, seed_rhs))
 
 
+def linear_dirichlet_data(n_el: int, p: int, a) -> tuple:
+    """(core, factors) of u(x, y, z) = a0 + a1 x + a2 y + a3 z on the full
+    tensor-product B-spline basis (n_el + p functions per direction, open
+    uniform knots): the constant has coefficients 1 and a coordinate the
+    Greville abscissae (averages of p consecutive interior knots), so the
+    tensor is exact; multilinear rank at most (2, 2, 2).  Input data of the
+    manufactured-solution runs with non-homogeneous Dirichlet conditions."""
+    knots = np.concatenate([np.zeros(p + 1), np.arange(1, n_el) / n_el, np.ones(p + 1)])
+    xi = np.array([knots[i + 1:i + p + 1].sum() / p for i in range(n_el + p)])
+    U = [np.stack([np.ones_like(xi), xi], axis=1) for _ in range(3)]
+    core = np.zeros((2, 2, 2))
+    core[0, 0, 0], core[1, 0, 0], core[0, 1, 0], core[0, 0, 1] = a
+    return core, U
+
+
 def random_rhs(n: int, rank: int, seed: int, ranks=None) -> dict:
     rng = np.random.default_rng(seed)
     r = tuple(ranks) if ranks is not None else (rank, rank, rank)
