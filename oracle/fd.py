@@ -70,27 +70,51 @@ class ExactFD:
 # Appendix B: approximate eigenpairs, Dirichlet at both ends
 # ---------------------------------------------------------------------------
 
-def subspace_dims(n_el: int, p: int):
-    """n = n_el + p - 2; n1 = dim V_h1 and n2 = dim V_h2 (Appendix B)."""
-    n = n_el + p - 2
-    if p % 2 == 1:
-        return n, n_el - 1, p - 1
-    return n, n_el, p - 2
+def subspace_dims(n_el: int, p: int, bc=(0, 0)):
+    """n = n_el + p - 2 + k0 + k1; n1 = dim V_h1 and n2 = dim V_h2 (Appendix
+    B): n1 = n_el - 1 + k0 + k1 for odd p, n_el for even p (the number of
+    interpolation points), n2 = n - n1 (the end constraints)."""
+    k0, k1 = bc
+    n = n_el + p - 2 + k0 + k1
+    n1 = n_el - 1 + k0 + k1 if p % 2 == 1 else n_el
+    return n, n1, n - n1
 
 
-def interpolation_points(n_el: int, p: int) -> np.ndarray:
-    """Breakpoints except 0 and 1 for odd p, span midpoints for even p."""
+def interpolation_points(n_el: int, p: int, bc=(0, 0)) -> np.ndarray:
+    """Breakpoints for odd p (the ends only where the condition is Neumann),
+    span midpoints for even p."""
+    k0, k1 = bc
     if p % 2 == 1:
-        return np.arange(1, n_el) / n_el
+        return np.arange(1 - k0, n_el + k1) / n_el
     return (np.arange(1, n_el + 1) - 0.5) / n_el
 
 
-def _constraints(n_el, p, at):
-    """Rows phi -> phi^(2k)(at), 1 <= k, 2k <= p - 1, on the Dirichlet basis."""
-    rows = [bspline.dirichlet_basis_at(n_el, p, [at], der=2 * k)[0]
-            for k in range(1, (p - 1) // 2 + 1)]
-    n = n_el + p - 2
-    return np.array(rows).reshape(-1, n)
+def _constraint_orders(p: int, neumann: int):
+    """Derivative orders fixed to zero at an end in V_h1 (Appendix B): the
+    even ones 2k (k >= 1, 2k <= p - 1) at a Dirichlet end (the value is
+    zero in the space already), the odd ones 2k + 1 <= p - 1 at a Neumann
+    end."""
+    if neumann:
+        return list(range(1, p, 2))
+    return list(range(2, p, 2))
+
+
+def _constraints(n_el, p, at, bc=(0, 0)):
+    """Rows phi -> phi^(d)(at) over the constrained orders d of that end, on
+    the basis of the space with flags bc."""
+    neumann = bc[0] if at == 0.0 else bc[1]
+    lo, hi = bspline.dof_range(n_el, p, bc)
+    kn = bspline.open_knots(n_el, p)
+    rows = [bspline.basis(kn, p, [at], d)[0, lo:hi] for d in _constraint_orders(p, neumann)]
+    return np.array(rows).reshape(-1, hi - lo)
+
+
+def _end_block(p: int, neumann: int) -> int:
+    """Number of leading (trailing) basis functions of the space that carry
+    the constrained derivatives at x = 0 (x = 1): the derivative of order d
+    there involves the first d + 1 functions of the full basis."""
+    orders = _constraint_orders(p, neumann)
+    return (max(orders) + 1 - (0 if neumann else 1)) if orders else 0
 
 
 def exact_eig(n_el: int, p: int, bc=(0, 0)):
@@ -106,46 +130,55 @@ def exact_eig(n_el: int, p: int, bc=(0, 0)):
     return U, np.where(lam < 1e-12 * lam.max(), 0.0, lam)
 
 
-def approx_eig(n_el: int, p: int):
-    """(U~, Lambda~, parts) of Appendix B for one direction.
+def approx_eig(n_el: int, p: int, bc=(0, 0)):
+    """(U~, Lambda~, parts) of Appendix B for one direction, on the space
+    with boundary flags bc = (k0, k1) (1 Neumann, 0 Dirichlet; the default is
+    the Dirichlet case the appendix starts with).
 
-    U~ = [V1 U1 | V2 U2] (n x n), Lambda~ = [Lambda1 ; Lambda2]."""
-    n, n1, n2 = subspace_dims(n_el, p)
+    U~ = [V1 U1 | V2 U2] (n x n), Lambda~ = [Lambda1 ; Lambda2]; the sines
+    are sin((j - k0/2 - k1/2) pi x + k0 pi/2) and Lambda1 = ((j - k0/2 -
+    k1/2) pi)^2 (with Neumann at both ends j = 1 is the constant,
+    eigenvalue 0)."""
+    k0, k1 = bc
+    n, n1, n2 = subspace_dims(n_el, p, bc)
     assert n_el > p, "Appendix B assumes n_el > p"
-    K = bspline.matrix(n_el, p, "stiff")
-    M = bspline.matrix(n_el, p, "mass")
-    D0 = _constraints(n_el, p, 0.0)
-    D1 = _constraints(n_el, p, 1.0)
+    K = bspline.matrix(n_el, p, "stiff", bc=bc)
+    M = bspline.matrix(n_el, p, "mass", bc=bc)
+    D0 = _constraints(n_el, p, 0.0, bc)
+    D1 = _constraints(n_el, p, 1.0, bc)
     D = np.vstack([D0, D1]) if n2 > 0 else np.zeros((0, n))
+    e0, e1 = _end_block(p, k0), _end_block(p, k1)
 
     # basis Phi0 u Phi u Phi1 of V_h1 (columns of V1)
     V1 = np.zeros((n, n1))
     col = 0
-    if n2 > 0:
-        N0 = sla.null_space(D0[:, :n2])              # Phi0 in span{b_1..b_n2}
-        V1[:n2, col:col + N0.shape[1]] = N0
+    if e0 > 0:
+        N0 = sla.null_space(D0[:, :e0])              # Phi0 in the span of the first e0 functions
+        V1[:e0, col:col + N0.shape[1]] = N0
         col += N0.shape[1]
-    for j in range(n2, n1):                          # Phi = {b_{n2+1}, .., b_{n1}}
+    for j in range(e0, n - e1):                      # Phi: single basis functions
         V1[j, col] = 1.0
         col += 1
-    if n2 > 0:
-        N1 = sla.null_space(D1[:, n1:])              # Phi1 in span{b_{n1+1}..b_n}
-        V1[n1:, col:col + N1.shape[1]] = N1
+    if e1 > 0:
+        N1 = sla.null_space(D1[:, n - e1:])          # Phi1 in the span of the last e1 functions
+        V1[n - e1:, col:col + N1.shape[1]] = N1
         col += N1.shape[1]
     assert col == n1
 
-    x = interpolation_points(n_el, p)
-    Bx = bspline.dirichlet_basis_at(n_el, p, x)       # Bx[j, l] = b_l(x_j)
+    x = interpolation_points(n_el, p, bc)
+    lo, hi = bspline.dof_range(n_el, p, bc)
+    Bx = bspline.basis(bspline.open_knots(n_el, p), p, x, 0)[:, lo:hi]   # Bx[j, l] = b_l(x_j)
     C = (Bx @ V1).T                                  # C[i, j] = v_i(x_j)
     jj = np.arange(1, n1 + 1)
-    Udft = np.sqrt(2.0) * np.sin(np.pi * np.outer(x, jj))   # [U_dft]_{i,j}
+    freq = jj - 0.5 * (k0 + k1)
+    Udft = np.sqrt(2.0) * np.sin(np.pi * np.outer(x, freq) + 0.5 * np.pi * k0)   # [U_dft]_{i,j}
     U1 = np.linalg.solve(C.T, Udft)                  # interpolation in V_h1
     # unit L^2 (= M) norm of every interpolated sine
     W1 = V1 @ U1
     scale1 = 1.0 / np.sqrt(np.einsum("ij,ij->j", W1, M @ W1))
     parts = {"V1": V1, "C": C, "Udft": Udft, "U1": U1, "D": D, "K": K, "M": M,
              "x": x, "n1": n1, "n2": n2, "scale1": scale1}
-    lam1 = (np.pi * jj) ** 2
+    lam1 = (np.pi * freq) ** 2
     if n2 > 0:
         V2 = np.linalg.solve(M, D.T)                 # M-orthogonal complement
         lam2, U2 = sla.eigh(V2.T @ K @ V2, V2.T @ M @ V2)
@@ -180,9 +213,7 @@ class LowRankFD:
             if exact:   # Algorithm 4 with the exact factorizations of Algorithm 3
                 U, lam = exact_eig(n_el[i], p, bcs[i])
             else:
-                if tuple(bcs[i]) != (0, 0):
-                    raise NotImplementedError("the Appendix B approximation is built for Dirichlet ends only")
-                U, lam, _ = approx_eig(n_el[i], p)
+                U, lam, _ = approx_eig(n_el[i], p, tuple(bcs[i]))
             self.Ut.append(U)
             self.lam.append(coef[i] * lam)
         self.lam_min = sum(np.min(l) for l in self.lam)

@@ -143,3 +143,64 @@ def test_workload_linear_data_matches_the_oracle():
         core, U = W.linear_dirichlet_data(n_el, p, (1.0, -2.0, 0.5, 3.0))
         ref = obc.linear_coefficients(n_el, p, (1.0, -2.0, 0.5, 3.0))
         np.testing.assert_allclose(Tucker(core, U).full(), ref.full(), rtol=0, atol=1e-14)
+
+
+# --- Appendix B with Neumann ends ---------------------------------------------
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("p", [2, 3, 4, 5])
+def test_appendix_b_structure_with_flags(bc, p):
+    """V_h1 has vanishing odd derivatives at Neumann ends and vanishing even
+    ones at Dirichlet ends; its dimension equals the number of interpolation
+    points (breakpoints without Dirichlet ends for odd p, midpoints for even
+    p); the interpolants of sin((j - k0/2 - k1/2) pi x + k0 pi/2) have unit
+    M-norm and Lambda1 = ((j - k0/2 - k1/2) pi)^2; V_h2 is M-orthogonal."""
+    n_el = 12
+    k0, k1 = bc
+    Ut, lam, P = fd.approx_eig(n_el, p, bc)
+    n, n1, n2 = fd.subspace_dims(n_el, p, bc)
+    assert n == n_el + p - 2 + k0 + k1 and Ut.shape == (n, n)
+    x = P["x"]
+    assert len(x) == n1
+    assert np.isclose(x[0], 0.0) == (p % 2 == 1 and k0 == 1)
+    assert np.isclose(x[-1], 1.0) == (p % 2 == 1 and k1 == 1)
+    kn = bspline.open_knots(n_el, p)
+    lo, hi = bspline.dof_range(n_el, p, bc)
+    W1 = Ut[:, :n1]
+    for end, k in ((0.0, k0), (1.0, k1)):
+        orders = range(1, p, 2) if k else range(2, p, 2)
+        for d in orders:
+            Dd = bspline.basis(kn, p, [end], d)[0, lo:hi]
+            assert np.abs(Dd @ W1).max() <= 1e-9 * np.abs(Dd).max() * np.abs(W1).max(), (end, d)
+    freq = np.arange(1, n1 + 1) - 0.5 * (k0 + k1)
+    sines = np.sin(np.pi * np.outer(x, freq) + 0.5 * np.pi * k0)
+    vals = bspline.basis(kn, p, x, 0)[:, lo:hi] @ W1
+    # the interpolants reproduce the sines up to their normalisation
+    ratio = vals / np.where(np.abs(sines) > 1e-8, sines, np.nan)
+    for j in range(n1):
+        r = ratio[:, j][~np.isnan(ratio[:, j])]
+        assert np.ptp(r) <= 1e-9 * np.abs(r).max(), j
+    M = bspline.matrix(n_el, p, "mass", bc=bc)
+    np.testing.assert_allclose(np.einsum("ij,ij->j", W1, M @ W1), 1.0, rtol=1e-12)
+    np.testing.assert_allclose(lam[:n1], (np.pi * freq) ** 2, rtol=1e-14)
+    if n2:
+        G = Ut.T @ M @ Ut
+        assert np.abs(G[:n1, n1:]).max() < 1e-12
+        np.testing.assert_allclose(G[n1:, n1:], np.eye(n2), atol=1e-12)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_appendix_b_flags_iterations_close_to_exact(p):
+    """The remark of Sec. 5 with Neumann ends: TPCG with the Appendix B
+    eigenpairs takes nearly as many iterations as with the exact ones
+    (weighted operator, flags (N,N), (N,D), (D,D), n_el = 16)."""
+    from oracle import tpcg as otpcg
+    n_el = 16
+    bcs = ((1, 1), (1, 0), (0, 0))
+    w = W.weighted_cp(n_el, p, 6, 2, 41, 42)
+    op = obc.operator(w, bcs)
+    n = [n_el + p - 2 + sum(b) for b in bcs]
+    f = Tucker(*W.random_tucker(n, (2, 2, 2), 43))
+    its = [otpcg.tpcg(op, fd.LowRankFD(n_el, p, 0.1, exact=ex, bcs=bcs), f, tol=1e-6, eps_min=1e-8)[1].iters
+           for ex in (False, True)]
+    assert abs(its[0] - its[1]) <= max(2, 0.2 * its[1]), its
