@@ -214,8 +214,8 @@ def mode_products_hbm(ctx, reps=5):
 def boundary_conditions(ctx, reps=3):
     """Solves with Neumann ends and non-homogeneous Dirichlet data (Appendix
     B flags; the lifting of the remark closing Sec. 3) at n_el = 128, p = 3:
-    Dirichlet at z = 0 and z = 1, Neumann on the four other faces, the
-    exact-eigenvector FD on those spaces.  (1) the Laplacian with the data
+    Dirichlet at z = 0 and z = 1, Neumann on the four other faces, the FD
+    with Appendix B's eigen-approximations on those spaces (dense).  (1) the Laplacian with the data
     of u = 1 + 3z and f = 0, whose discrete solution is u itself: relative
     error of the TPCG solution; (2) the deformed recipe's 9 weighted terms
     with rhs of rank 5 and Dirichlet data of rank 2 (seeded): iterations and
@@ -227,7 +227,7 @@ def boundary_conditions(ctx, reps=3):
     import workloads as W
     n_el, p = 128, 3
     bcs = ((1, 1), (1, 1), (0, 0))
-    out = {"n_el": n_el, "p": p, "flags": [list(b) for b in bcs]}
+    out = {"n_el": n_el, "p": p, "flags": [list(b) for b in bcs], "fd_eigenpairs": "appendix_b_dense"}
     w = W.laplace_cube(n_el, p)
     gcore, gU = W.linear_dirichlet_data(n_el, p, (1.0, 0.0, 0.0, 3.0))
     op, P = problem.operator_bc(ctx, w, bcs), problem.preconditioner_bc(ctx, w, bcs)

@@ -213,6 +213,18 @@ tk_status fd_setup_exact(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double e
  * than 0 and 1; the rest as fd_setup_exact. */
 tk_status fd_setup_exact_bc(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec,
                             const double coef[3], const int32_t bc[6], tk_prec** out, int32_t* R_P);
+
+/* The Appendix B eigen-approximations on the spaces with boundary flags
+ * bc[2k], bc[2k+1] (Neumann ends: V_h1 with vanishing odd derivatives there,
+ * the sines sin((j - k0/2 - k1/2) pi x + k0 pi/2) interpolated at the
+ * breakpoints or span midpoints, Lambda1 = ((j - k0/2 - k1/2) pi)^2; V_h2 its
+ * M-orthogonal complement with exact eigenpairs), built densely on the host
+ * (O(n^3) per direction) and applied by fd_precond like fd_setup_exact's
+ * (two matrix-core GEMMs per mode).  With all flags 0 it is fd_setup's
+ * approximation without the sine transforms.  p >= 2, p < n_el <= 4096;
+ * EINVAL on bad arguments or a singular operator. */
+tk_status fd_setup_bc(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec, const double coef[3],
+                      const int32_t bc[6], tk_prec** out, int32_t* R_P);
 void tk_prec_free(tk_prec* P);
 
 /* R_P, lambda_min, lambda_max, E_{R_P}(M_P); alpha/omega (R_P doubles each,
@@ -243,6 +255,12 @@ tk_status fd_precond_arith(tk_ctx* ctx, const tk_prec* P, const tk_tucker* s, in
  * are left untouched. */
 tk_status tk_prec_direction(const tk_prec* P, int32_t k, int32_t* n, int32_t* n1, int32_t* n2,
                             double* lam, double* g, double* E, double* v2u2);
+
+/* Host-only inspection of fd_setup_bc's direction data: n, lam (n) and the
+ * dense U~ (n x n, column-major, caller-owned; either may be NULL) for the
+ * space with flags (k0, k1).  EINVAL on bad arguments. */
+tk_status tk_fd_direction_dense_host(int32_t n_el, int32_t p, double coef, int32_t k0, int32_t k1, int32_t* n,
+                                     double* lam, double* Ut);
 
 /* ---- truncation (Algorithm 1) --------------------------------------------- */
 

@@ -1560,8 +1560,10 @@ tk_status fd_setup(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_pre
 
 // fd_setup_exact on the spaces with boundary flags bc[2k], bc[2k+1] (null:
 // Dirichlet everywhere)
+// approx: the Appendix B eigen-approximations on the same spaces, built
+// densely on the host (fd_approx_dense), instead of the exact eigenpairs
 static tk_status setup_exact(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec, const double coef[3],
-                             const int32_t* bc, tk_prec** out, int32_t* R_P) {
+                             const int32_t* bc, tk_prec** out, int32_t* R_P, bool approx = false) {
   if (!ctx || !n_el || !out || !(eps_prec > 0.0)) return TK_EINVAL;
   *out = nullptr;
   return guarded(ctx, [&]() {
@@ -1575,6 +1577,17 @@ static tk_status setup_exact(tk_ctx* ctx, const int32_t n_el[3], int32_t p, doub
       std::vector<double> C;
       int n = 0;
       const int k0 = bc ? bc[2 * k] : 0, k1 = bc ? bc[2 * k + 1] : 0;
+      if (approx) {
+        std::vector<double> Ut;
+        if (!fd_approx_dense(n_el[k], p, c, k0, k1, Ut, P->lam_exact[k], n, msg)) throw Error(TK_EINVAL, msg);
+        P->n_exact[k] = n;
+        P->Ud[k] = alloc(ctx, (size_t)n * n);
+        h2d(ctx, P->Ud[k]->p, Ut.data(), (size_t)n * n);
+        const auto& l = P->lam_exact[k];
+        P->lam_min += *std::min_element(l.begin(), l.end());
+        P->lam_max += *std::max_element(l.begin(), l.end());
+        continue;
+      }
       if (!fd_exact_pencil(n_el[k], p, c, C, L[k], n, msg, k0, k1)) throw Error(TK_EINVAL, msg);
       P->n_exact[k] = n;
       // eigenpairs of C with the library's symmetric eigensolver
@@ -1634,6 +1647,30 @@ tk_status fd_setup_exact_bc(tk_ctx* ctx, const int32_t n_el[3], int32_t p, doubl
   for (int i = 0; i < 6; ++i)
     if (bc[i] != 0 && bc[i] != 1) return TK_EINVAL;
   return setup_exact(ctx, n_el, p, eps_prec, coef, bc, out, R_P);
+}
+
+tk_status fd_setup_bc(tk_ctx* ctx, const int32_t n_el[3], int32_t p, double eps_prec, const double coef[3],
+                      const int32_t bc[6], tk_prec** out, int32_t* R_P) {
+  if (!bc) return TK_EINVAL;
+  for (int i = 0; i < 6; ++i)
+    if (bc[i] != 0 && bc[i] != 1) return TK_EINVAL;
+  return setup_exact(ctx, n_el, p, eps_prec, coef, bc, out, R_P, true);
+}
+
+tk_status tk_fd_direction_dense_host(int32_t n_el, int32_t p, double coef, int32_t k0, int32_t k1, int32_t* n,
+                                     double* lam, double* Ut) {
+  try {
+    std::vector<double> U, l;
+    std::string msg;
+    int nn = 0;
+    if (!(coef > 0.0) || !fd_approx_dense(n_el, p, coef, k0, k1, U, l, nn, msg)) return TK_EINVAL;
+    if (n) *n = nn;
+    if (lam) std::copy(l.begin(), l.end(), lam);
+    if (Ut) std::copy(U.begin(), U.end(), Ut);
+  } catch (...) {
+    return TK_ENOMEM;
+  }
+  return TK_OK;
 }
 
 void tk_prec_free(tk_prec* P) { delete P; }

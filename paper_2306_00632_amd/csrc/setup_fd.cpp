@@ -488,6 +488,272 @@ bool fd_exact_pencil(int n_el, int p, double coef, std::vector<double>& C, std::
   return true;
 }
 
+// Appendix B on the space with boundary flags (k0, k1), built densely:
+// V_h1 = {phi : phi^(d)(e) = 0 for the constrained orders d at each end e}
+// (even orders >= 2 at a Dirichlet end, odd orders at a Neumann end, all
+// d <= p - 1), spanned by Phi0 (combinations of the first e0 functions in
+// the kernel of the constraints at 0), single functions in the middle and
+// Phi1 (the last e1 functions, constraints at 1); the sines
+// sqrt(2) sin((j - (k0+k1)/2) pi x + k0 pi/2) interpolated in V_h1 at the
+// breakpoints (odd p; an end only where it is Neumann) or span midpoints
+// (even p), each scaled to unit M-norm, with Lambda1 = ((j - (k0+k1)/2) pi)^2;
+// V2 = M^{-1} D^T spans the M-orthogonal complement and carries the exact
+// eigenpairs of its projected pencil.  Ut (n x n, column-major) =
+// [V1 U1 | V2 U2] and lam (n) are for (coef K, M).
+bool fd_approx_dense(int n_el, int p, double coef, int k0, int k1, std::vector<double>& Ut,
+                     std::vector<double>& lam, int& n, std::string& msg) {
+  if (p < 2 || n_el <= p || n_el > 4096) {
+    msg = "fd_setup_bc: need p >= 2 and p < n_el <= 4096";
+    return false;
+  }
+  if ((k0 != 0 && k0 != 1) || (k1 != 0 && k1 != 1)) {
+    msg = "fd_setup_bc: boundary flags must be 0 (Dirichlet) or 1 (Neumann)";
+    return false;
+  }
+  n = n_el + p - 2 + k0 + k1;
+  const int n1 = (p % 2 == 1) ? n_el - 1 + k0 + k1 : n_el;
+  const int n2 = n - n1;
+  const int sh = 1 - k0;  // full-basis index of space index 0
+  const double unit[4] = {1.0, 0.0, 0.0, 0.0};
+  std::vector<double> Mb(size_t(2 * p + 1) * n), Kb(size_t(2 * p + 1) * n);
+  assemble_band(n_el, p, 0, unit, Mb.data(), k0, k1);
+  assemble_band(n_el, p, 1, unit, Kb.data(), k0, k1);
+  std::vector<double> LM;
+  if (!band_cholesky(Mb, n, p, LM)) {
+    msg = "fd_setup_bc: mass matrix not positive definite";
+    return false;
+  }
+  const auto kn = open_knots(n_el, p);
+  // constraint rows (over the space's n functions) at an end
+  auto orders = [&](int neumann) {
+    std::vector<int> o;
+    for (int d = neumann ? 1 : 2; d < p; d += 2) o.push_back(d);
+    return o;
+  };
+  auto rows_at = [&](double x, int neumann) {
+    const auto od = orders(neumann);
+    const int span = find_span(kn, p, x);
+    std::vector<double> vals(size_t(p + 1) * (p + 1));
+    span_basis(kn, p, span, x, p, vals.data());
+    std::vector<std::vector<double>> R;
+    for (int d : od) {
+      std::vector<double> r(n, 0.0);
+      for (int a = 0; a <= p; ++a) {
+        const int i = span - p + a - sh;
+        if (i >= 0 && i < n) r[i] = vals[size_t(d) * (p + 1) + a];
+      }
+      R.push_back(r);
+    }
+    return R;
+  };
+  const auto D0 = rows_at(0.0, k0), D1 = rows_at(1.0, k1);
+  if (int(D0.size() + D1.size()) != n2) {
+    msg = "fd_setup_bc: constraint count does not match the interpolation points";
+    return false;
+  }
+  const auto o0 = orders(k0), o1 = orders(k1);
+  const int e0 = o0.empty() ? 0 : o0.back() + k0, e1 = o1.empty() ? 0 : o1.back() + k1;
+  // kernel of a c x e block (rows of D restricted to columns [c0, c0 + e)):
+  // the last e - c columns of the full Q of a Householder QR of its transpose
+  auto kernel = [&](const std::vector<std::vector<double>>& D, int col0, int e) {
+    const int c = int(D.size());
+    std::vector<double> A(size_t(e) * c);  // e x c, column-major
+    for (int r = 0; r < c; ++r)
+      for (int i = 0; i < e; ++i) A[size_t(r) * e + i] = D[r][col0 + i];
+    std::vector<double> Q(size_t(e) * e, 0.0);
+    for (int i = 0; i < e; ++i) Q[size_t(i) * e + i] = 1.0;
+    for (int k = 0; k < c; ++k) {
+      std::vector<double> v(e, 0.0);
+      double nrm = 0.0;
+      for (int i = k; i < e; ++i) nrm += A[size_t(k) * e + i] * A[size_t(k) * e + i];
+      nrm = std::sqrt(nrm);
+      if (nrm == 0.0) continue;
+      const double alpha = A[size_t(k) * e + k] > 0 ? -nrm : nrm;
+      for (int i = k; i < e; ++i) v[i] = A[size_t(k) * e + i];
+      v[k] -= alpha;
+      double vv = 0.0;
+      for (double t : v) vv += t * t;
+      if (vv == 0.0) continue;
+      for (int j = k; j < c; ++j) {  // A <- H A
+        double sdot = 0.0;
+        for (int i = k; i < e; ++i) sdot += v[i] * A[size_t(j) * e + i];
+        sdot = 2.0 * sdot / vv;
+        for (int i = k; i < e; ++i) A[size_t(j) * e + i] -= sdot * v[i];
+      }
+      for (int j = 0; j < e; ++j) {  // G <- H G: G = H_{c-1} ... H_0 = Q^T
+        double sdot = 0.0;
+        for (int i = k; i < e; ++i) sdot += Q[size_t(i) * e + j] * v[i];
+        sdot = 2.0 * sdot / vv;
+        for (int i = k; i < e; ++i) Q[size_t(i) * e + j] -= sdot * v[i];
+      }
+    }
+    return Q;  // Q^T, row-major e x e: kernel vector j (j >= c) is its row j
+  };
+  // V1 as (row, column, value) triplets
+  struct Ent { int r, c; double v; };
+  std::vector<Ent> V1;
+  int col = 0;
+  if (e0 > 0) {
+    const auto Q = kernel(D0, 0, e0);
+    for (int j = int(D0.size()); j < e0; ++j, ++col)
+      for (int i = 0; i < e0; ++i) V1.push_back({i, col, Q[size_t(j) * e0 + i]});
+  }
+  for (int r = e0; r < n - e1; ++r, ++col) V1.push_back({r, col, 1.0});
+  if (e1 > 0) {
+    const auto Q = kernel(D1, n - e1, e1);
+    for (int j = int(D1.size()); j < e1; ++j, ++col)
+      for (int i = 0; i < e1; ++i) V1.push_back({n - e1 + i, col, Q[size_t(j) * e1 + i]});
+  }
+  if (col != n1) {
+    msg = "fd_setup_bc: V_h1 basis has the wrong dimension";
+    return false;
+  }
+  // A = Bx V1 (n1 x n1, row-major): the V_h1 basis at the interpolation points
+  std::vector<double> xs(n1);
+  for (int i = 0; i < n1; ++i) xs[i] = (p % 2 == 1) ? double(i + 1 - k0) / n_el : (i + 0.5) / n_el;
+  std::vector<std::vector<Ent>> byrow(n);
+  for (const auto& t : V1) byrow[t.r].push_back(t);
+  std::vector<double> A(size_t(n1) * n1, 0.0), vals(p + 1);
+  for (int i = 0; i < n1; ++i) {
+    const int span = find_span(kn, p, xs[i]);
+    span_basis(kn, p, span, xs[i], 0, vals.data());
+    for (int a = 0; a <= p; ++a) {
+      const int r = span - p + a - sh;
+      if (r < 0 || r >= n) continue;
+      for (const auto& t : byrow[r]) A[size_t(i) * n1 + t.c] += vals[a] * t.v;
+    }
+  }
+  // U1 = A^{-1} Udft (LU with partial pivoting), row-major n1 x n1
+  const double kPi = 3.14159265358979323846, kap = 0.5 * (k0 + k1);
+  std::vector<double> U1(size_t(n1) * n1);
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j)
+      U1[size_t(i) * n1 + j] = std::sqrt(2.0) * std::sin(kPi * (j + 1 - kap) * xs[i] + 0.5 * kPi * k0);
+  std::vector<int> piv(n1);
+  for (int k = 0; k < n1; ++k) {
+    int pr = k;
+    for (int i = k + 1; i < n1; ++i)
+      if (std::fabs(A[size_t(i) * n1 + k]) > std::fabs(A[size_t(pr) * n1 + k])) pr = i;
+    if (A[size_t(pr) * n1 + k] == 0.0) {
+      msg = "fd_setup_bc: singular collocation matrix";
+      return false;
+    }
+    if (pr != k) {
+      for (int j = 0; j < n1; ++j) std::swap(A[size_t(k) * n1 + j], A[size_t(pr) * n1 + j]);
+      for (int j = 0; j < n1; ++j) std::swap(U1[size_t(k) * n1 + j], U1[size_t(pr) * n1 + j]);
+    }
+    const double d = A[size_t(k) * n1 + k];
+    for (int i = k + 1; i < n1; ++i) {
+      const double f = A[size_t(i) * n1 + k] / d;
+      if (f == 0.0) continue;
+      for (int j = k + 1; j < n1; ++j) A[size_t(i) * n1 + j] -= f * A[size_t(k) * n1 + j];
+      for (int j = 0; j < n1; ++j) U1[size_t(i) * n1 + j] -= f * U1[size_t(k) * n1 + j];
+    }
+  }
+  for (int k = n1 - 1; k >= 0; --k) {
+    for (int j = 0; j < n1; ++j) {
+      double sacc = U1[size_t(k) * n1 + j];
+      for (int i = k + 1; i < n1; ++i) sacc -= A[size_t(k) * n1 + i] * U1[size_t(i) * n1 + j];
+      U1[size_t(k) * n1 + j] = sacc / A[size_t(k) * n1 + k];
+    }
+  }
+  // W1 = V1 U1, columns scaled to unit M-norm
+  Ut.assign(size_t(n) * n, 0.0);
+  lam.assign(n, 0.0);
+  for (const auto& t : V1)
+    for (int j = 0; j < n1; ++j) Ut[size_t(j) * n + t.r] += t.v * U1[size_t(t.c) * n1 + j];
+  std::vector<double> mw(n);
+  for (int j = 0; j < n1; ++j) {
+    double* w = Ut.data() + size_t(j) * n;
+    band_matvec(Mb, n, p, w, mw.data());
+    double nm = 0.0;
+    for (int i = 0; i < n; ++i) nm += w[i] * mw[i];
+    if (!(nm > 0.0)) {
+      msg = "fd_setup_bc: an interpolated sine has zero norm";
+      return false;
+    }
+    const double sc = 1.0 / std::sqrt(nm);
+    for (int i = 0; i < n; ++i) w[i] *= sc;
+    const double f = kPi * (j + 1 - kap);
+    lam[j] = coef * f * f;
+  }
+  if (n2 > 0) {
+    // V2 = M^{-1} D^T, then the pencil (V2^T K V2, V2^T M V2) by Cholesky and Jacobi
+    std::vector<std::vector<double>> D(D0);
+    D.insert(D.end(), D1.begin(), D1.end());
+    std::vector<std::vector<double>> V2(n2);
+    for (int c = 0; c < n2; ++c) {
+      V2[c] = D[c];
+      band_cholesky_solve(LM, n, p, V2[c]);
+    }
+    std::vector<double> K2(size_t(n2) * n2), M2(size_t(n2) * n2), kv(n), mv(n);
+    for (int b = 0; b < n2; ++b) {
+      band_matvec(Kb, n, p, V2[b].data(), kv.data());
+      band_matvec(Mb, n, p, V2[b].data(), mv.data());
+      for (int a = 0; a < n2; ++a) {
+        double sk = 0.0, sm = 0.0;
+        for (int i = 0; i < n; ++i) {
+          sk += V2[a][i] * kv[i];
+          sm += V2[a][i] * mv[i];
+        }
+        K2[size_t(a) * n2 + b] = sk;
+        M2[size_t(a) * n2 + b] = sm;
+      }
+    }
+    std::vector<double> L2(size_t(n2) * n2, 0.0);  // M2 = L2 L2^T, row-major lower
+    for (int i = 0; i < n2; ++i)
+      for (int j = 0; j <= i; ++j) {
+        double sacc = M2[size_t(i) * n2 + j];
+        for (int k = 0; k < j; ++k) sacc -= L2[size_t(i) * n2 + k] * L2[size_t(j) * n2 + k];
+        if (i == j) {
+          if (!(sacc > 0.0)) {
+            msg = "fd_setup_bc: V2 Gram matrix not positive definite";
+            return false;
+          }
+          L2[size_t(i) * n2 + i] = std::sqrt(sacc);
+        } else {
+          L2[size_t(i) * n2 + j] = sacc / L2[size_t(j) * n2 + j];
+        }
+      }
+    // C2 = L2^{-1} K2 L2^{-T}
+    std::vector<double> X(K2);
+    for (int c = 0; c < n2; ++c)  // X <- L2^{-1} X (column c)
+      for (int i = 0; i < n2; ++i) {
+        double sacc = X[size_t(i) * n2 + c];
+        for (int k = 0; k < i; ++k) sacc -= L2[size_t(i) * n2 + k] * X[size_t(k) * n2 + c];
+        X[size_t(i) * n2 + c] = sacc / L2[size_t(i) * n2 + i];
+      }
+    std::vector<double> C2(size_t(n2) * n2);
+    for (int r = 0; r < n2; ++r)  // C2 <- X L2^{-T} (row r: solve L2 y = X[r, :]^T)
+      for (int i = 0; i < n2; ++i) {
+        double sacc = X[size_t(r) * n2 + i];
+        for (int k = 0; k < i; ++k) sacc -= L2[size_t(i) * n2 + k] * C2[size_t(r) * n2 + k];
+        C2[size_t(r) * n2 + i] = sacc / L2[size_t(i) * n2 + i];
+      }
+    for (int a = 0; a < n2; ++a)
+      for (int b = a + 1; b < n2; ++b) {
+        const double v = 0.5 * (C2[size_t(a) * n2 + b] + C2[size_t(b) * n2 + a]);
+        C2[size_t(a) * n2 + b] = C2[size_t(b) * n2 + a] = v;
+      }
+    std::vector<double> Qs;
+    small_jacobi(C2, n2, Qs);
+    for (int c = 0; c < n2; ++c) {
+      // U2 column c = L2^{-T} Qs[:, c]
+      std::vector<double> u(n2);
+      for (int i = n2 - 1; i >= 0; --i) {
+        double sacc = Qs[size_t(i) * n2 + c];
+        for (int k = i + 1; k < n2; ++k) sacc -= L2[size_t(k) * n2 + i] * u[k];
+        u[i] = sacc / L2[size_t(i) * n2 + i];
+      }
+      double* out = Ut.data() + size_t(n1 + c) * n;
+      for (int b = 0; b < n2; ++b)
+        for (int i = 0; i < n; ++i) out[i] += V2[b][i] * u[b];
+      lam[n1 + c] = coef * C2[size_t(c) * n2 + c];
+    }
+  }
+  return true;
+}
+
 void fd_exact_vectors(const std::vector<double>& L, int n, int p, double* Q) {
   for (int c = 0; c < n; ++c) {
     double* x = Q + size_t(c) * n;

@@ -87,6 +87,11 @@ bool fd_direction_setup(int n_el, int p, double coef, FdDirection& d, std::strin
 // eigenvectors Q is M-orthonormal.
 bool fd_exact_pencil(int n_el, int p, double coef, std::vector<double>& C, std::vector<double>& L, int& n,
                      std::string& msg, int k0 = 0, int k1 = 0);
+// Appendix B eigen-approximations (U~, Lambda~) of (coef K, M) on the space
+// with boundary flags (k0, k1), built densely on the host: Ut n x n
+// column-major (M-orthonormal interpolated sines, then V2 U2), lam n.
+bool fd_approx_dense(int n_el, int p, double coef, int k0, int k1, std::vector<double>& Ut,
+                     std::vector<double>& lam, int& n, std::string& msg);
 // Q (n x n, column-major) <- L^{-T} Q
 void fd_exact_vectors(const std::vector<double>& L, int n, int p, double* Q);
 

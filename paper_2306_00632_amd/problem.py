@@ -50,10 +50,11 @@ def operator_bc(ctx, w, bcs) -> tk.Operator:
     return tk.Operator.create(ctx, w.p, n, bands, w.nnz)
 
 
-def preconditioner_bc(ctx, w, bcs, eps_prec=0.1, coef=(1.0, 1.0, 1.0)) -> tk.Preconditioner:
-    """Exact-eigenvector FD (Algorithm 4 with Algorithm 3's factorizations) on
-    the spaces with flags bcs[k]."""
-    return tk.Preconditioner.create(ctx, w.n_el, w.p, eps_prec, coef, exact=True, bcs=bcs)
+def preconditioner_bc(ctx, w, bcs, eps_prec=0.1, coef=(1.0, 1.0, 1.0), exact=False) -> tk.Preconditioner:
+    """FD (Algorithm 4) on the spaces with flags bcs[k]: the Appendix B
+    eigen-approximations with Neumann ends (default) or the exact
+    eigenpairs (Algorithm 3's factorizations), both applied densely."""
+    return tk.Preconditioner.create(ctx, w.n_el, w.p, eps_prec, coef, exact=exact, bcs=bcs)
 
 
 def lifted_rhs(ctx, w, bcs, g_core, g_factors, f=None, op_full=None) -> tk.Tucker:

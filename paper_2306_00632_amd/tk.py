@@ -72,6 +72,8 @@ EXPORTS = {
     "fd_setup": (C.c_int32, [vp, i32p, C.c_int32, C.c_double, dp, C.POINTER(vp), i32p]),
     "fd_setup_exact": (C.c_int32, [vp, i32p, C.c_int32, C.c_double, dp, C.POINTER(vp), i32p]),
     "fd_setup_exact_bc": (C.c_int32, [vp, i32p, C.c_int32, C.c_double, dp, i32p, C.POINTER(vp), i32p]),
+    "fd_setup_bc": (C.c_int32, [vp, i32p, C.c_int32, C.c_double, dp, i32p, C.POINTER(vp), i32p]),
+    "tk_fd_direction_dense_host": (C.c_int32, [C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_int32, i32p, dp, dp]),
     "tk_prec_free": (None, [vp]),
     "tk_prec_info": (C.c_int32, [vp, i32p, dp, dp, dp, dp, dp]),
     "tk_prec_direction": (C.c_int32, [vp, C.c_int32, i32p, i32p, i32p, dp, dp, dp, dp]),
@@ -139,6 +141,18 @@ def assemble_1d_bc(n_el: int, p: int, kind: str, weight=(1.0, 0.0, 0.0, 0.0), bc
     if st != TK_OK:
         raise TkError(st, "tk_assemble_1d_bc")
     return band
+
+
+def fd_direction_dense_host(n_el: int, p: int, coef: float = 1.0, bc=(0, 0)):
+    """(U~, lam) of fd_setup_bc for one direction (host only)."""
+    n = n_el + p - 2 + bc[0] + bc[1]
+    lam = np.zeros(n)
+    Ut = np.zeros(n * n)
+    nn = C.c_int32()
+    st = lib().tk_fd_direction_dense_host(n_el, p, coef, int(bc[0]), int(bc[1]), C.byref(nn), _ptr(lam), _ptr(Ut))
+    if st != TK_OK:
+        raise TkError(st, "tk_fd_direction_dense_host")
+    return Ut.reshape(n, n, order="F"), lam
 
 
 def load_vector_1d(n_el: int, p: int, weight) -> np.ndarray:
@@ -363,17 +377,17 @@ class Preconditioner(_Handle):
     def create(cls, ctx, n_el, p, eps_prec=0.1, coef=(1.0, 1.0, 1.0), exact=False, bcs=None) -> "Preconditioner":
         """Appendix B eigen-approximations (fd_setup), or with exact=True the
         exact generalized eigenpairs applied as dense GEMMs (fd_setup_exact);
-        bcs = ((k0, k1),) * 3 boundary flags (exact only: fd_setup_exact_bc)."""
+        with boundary flags bcs = ((k0, k1),) * 3 both are built densely on
+        those spaces (fd_setup_bc, fd_setup_exact_bc)."""
         ne = (C.c_int32 * 3)(*((n_el,) * 3 if np.isscalar(n_el) else n_el))
         cf = np.asarray(coef, dtype=np.float64)
         h = vp()
         R = C.c_int32()
         if bcs is not None:
-            if not exact:
-                raise ValueError("boundary flags need the exact-eigenvector preconditioner")
+            # Appendix B (fd_setup_bc) or exact eigenpairs (fd_setup_exact_bc), dense, on the flagged spaces
             flags = (C.c_int32 * 6)(*[int(f) for b in bcs for f in b])
-            ctx.check(lib().fd_setup_exact_bc(ctx.h, ne, p, eps_prec, _ptr(cf), flags, C.byref(h), C.byref(R)),
-                      "fd_setup_exact_bc")
+            name = "fd_setup_exact_bc" if exact else "fd_setup_bc"
+            ctx.check(getattr(lib(), name)(ctx.h, ne, p, eps_prec, _ptr(cf), flags, C.byref(h), C.byref(R)), name)
             return cls(ctx, h)
         name = "fd_setup_exact" if exact else "fd_setup"
         ctx.check(getattr(lib(), name)(ctx.h, ne, p, eps_prec, _ptr(cf), C.byref(h), C.byref(R)), name)

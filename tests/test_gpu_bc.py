@@ -8,7 +8,10 @@ against the oracle (oracle/bc.py, pinned in test_oracle_bc.py):
   full tensor (1e-12) at a tiny size;
 * the exact-eigenvector FD with flags against the oracle's LowRankFD with
   exact eigenpairs on the same spaces, factor columns at 1e-9 (independent
-  eigensolvers and Remez solvers on both sides);
+  eigensolvers and Remez solvers on both sides), and the Appendix B one
+  (fd_setup_bc) against the oracle's approximate eigenpairs at 1e-8; with
+  all flags Dirichlet the dense Appendix B path against the sine-transform
+  path (1e-9);
 * TPCG with that preconditioner and the lifted rhs: the manufactured linear
   solution u = 1 + 3z (Dirichlet at z = 0 and 1, Neumann on the other
   faces), which the discrete solution reproduces exactly, to the solver
@@ -83,22 +86,62 @@ def test_exact_fd_bc(ctx, bcs, p):
     assert rel(got.full(), ref.full()) < 1e-9
 
 
+@pytest.mark.parametrize("bcs,p", [(((1, 1), (1, 1), (0, 0)), 3), (((1, 0), (0, 1), (0, 0)), 2),
+                                   (((0, 1), (1, 1), (1, 0)), 5)])
+def test_appendix_b_fd_bc(ctx, bcs, p):
+    """fd_setup_bc (Appendix B with Neumann flags, dense) against the oracle's
+    LowRankFD with approximate eigenpairs on the same spaces (factor columns
+    U~ D_j U~^T S, independent of eigenvector signs, 1e-8)."""
+    from paper_2306_00632_amd import tk
+    n_el = 16
+    say(f"Appendix B fd with flags {bcs} p={p}")
+    Pg = tk.Preconditioner.create(ctx, n_el, p, 0.1, bcs=bcs)
+    Po = ofd.LowRankFD(n_el, p, 0.1, bcs=bcs)
+    assert Pg.info()["R_P"] == Po.R_P
+    n = [n_el + p - 2 + sum(b) for b in bcs]
+    core, U = W.random_tucker(n, (3, 2, 4), 92)
+    got = to_oracle(tk.fd_precond(ctx, Pg, tk.Tucker.from_host(ctx, core, U)))
+    ref = Po.apply(T.Tucker(core, U))
+    for k in range(3):
+        np.testing.assert_allclose(got.U[k], ref.U[k], rtol=0, atol=1e-8 * np.abs(ref.U[k]).max())
+
+
+@pytest.mark.parametrize("n_el,p", [(16, 3), (32, 2), (64, 5)])
+def test_dense_appendix_b_equals_sine_transform_path(ctx, n_el, p):
+    """With all flags Dirichlet the dense Appendix B preconditioner
+    (fd_setup_bc) and the sine-transform one (fd_setup) apply the same
+    operator: two independent constructions of Algorithm 4 (1e-9)."""
+    from paper_2306_00632_amd import tk
+    say(f"dense vs sine-transform Appendix B n_el={n_el} p={p}")
+    Pd = tk.Preconditioner.create(ctx, n_el, p, 0.1, bcs=((0, 0),) * 3)
+    Pf = tk.Preconditioner.create(ctx, n_el, p, 0.1)
+    n = n_el + p - 2
+    core, U = W.random_tucker(n, (2, 3, 2), 93)
+    s = tk.Tucker.from_host(ctx, core, U)
+    a, b = to_oracle(tk.fd_precond(ctx, Pd, s)), to_oracle(tk.fd_precond(ctx, Pf, s))
+    for k in range(3):
+        np.testing.assert_allclose(a.U[k], b.U[k], rtol=0, atol=1e-9 * np.abs(b.U[k]).max())
+
+
 def test_all_neumann_rejected(ctx):
     from paper_2306_00632_amd import tk
     with pytest.raises(tk.TkError):
         tk.Preconditioner.create(ctx, 8, 2, 0.1, exact=True, bcs=((1, 1),) * 3)
+    with pytest.raises(tk.TkError):
+        tk.Preconditioner.create(ctx, 8, 2, 0.1, bcs=((1, 1),) * 3)
 
 
+@pytest.mark.parametrize("exact", [False, True])
 @pytest.mark.parametrize("n_el,p", [(8, 2), (8, 3), (64, 3)])
-def test_tpcg_manufactured_linear_solution(ctx, n_el, p):
+def test_tpcg_manufactured_linear_solution(ctx, n_el, p, exact):
     from paper_2306_00632_amd import problem, tk
     w = W.laplace_cube(n_el, p)
     bcs = ((1, 1), (1, 1), (0, 0))
     g = obc.linear_coefficients(n_el, p, (1.0, 0.0, 0.0, 3.0))
-    say(f"tpcg manufactured u = 1 + 3z, n_el={n_el} p={p}")
+    say(f"tpcg manufactured u = 1 + 3z, n_el={n_el} p={p} exact={exact}")
     f = problem.lifted_rhs(ctx, w, bcs, g.core, g.U)
-    x, info = tk.tpcg_solve(ctx, problem.operator_bc(ctx, w, bcs), problem.preconditioner_bc(ctx, w, bcs), f,
-                            tol=1e-8)
+    x, info = tk.tpcg_solve(ctx, problem.operator_bc(ctx, w, bcs),
+                            problem.preconditioner_bc(ctx, w, bcs, exact=exact), f, tol=1e-8)
     ref = obc.restrict(g, n_el, p, bcs)
     err = rel(to_oracle_plain(x).full(), ref.full())
     say(f"   iters={info['iters']} rank={info['rank']} rel_err={err:.2e}")
@@ -117,7 +160,7 @@ def test_tpcg_weighted_mixed_flags_against_dense(ctx):
     say("tpcg weighted operator, mixed flags, random f and Dirichlet data")
     f = problem.lifted_rhs(ctx, w, bcs, g.core, g.U, f=tk.Tucker.from_host(ctx, fc, fU))
     x, info = tk.tpcg_solve(ctx, problem.operator_bc(ctx, w, bcs), problem.preconditioner_bc(ctx, w, bcs), f,
-                            tol=1e-9)
+                            tol=1e-9)   # Appendix B with the flags
     rhs = obc.lifted_rhs(w, bcs, g, T.Tucker(fc, fU))
     xd = dense_solve(obc.operator(w, bcs), rhs.full())
     err = rel(to_oracle_plain(x).full(), xd)

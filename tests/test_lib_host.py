@@ -138,3 +138,29 @@ def test_assemble_1d_bc(bc, p):
         ref = bspline.matrix(11, p, kind, wgt, bc=bc)
         assert A.shape == ref.shape
         assert np.abs(A - ref).max() <= 1e-13 * np.abs(ref).max(), kind
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6])
+def test_fd_direction_dense_matches_oracle(bc, p):
+    """fd_setup_bc's host construction of Appendix B with flags against the
+    oracle's approx_eig on the same space: the interpolated sines (V1 U1
+    columns, basis-independent) at 1e-12, Lambda1 exactly, and the V_h2
+    block through its projector and eigenvalues (its columns are unique up
+    to sign) at 1e-8 (M^{-1} D^T with derivatives up to p - 1 is the
+    ill-conditioned part)."""
+    from oracle import fd as ofd
+    from paper_2306_00632_amd import tk
+    for n_el in (8, 13, 32):
+        if n_el <= p:
+            continue
+        U, lam = tk.fd_direction_dense_host(n_el, p, 1.0, bc)
+        Uo, lamo, _ = ofd.approx_eig(n_el, p, bc)
+        n1 = ofd.subspace_dims(n_el, p, bc)[1]
+        scale = np.abs(Uo).max()
+        assert np.abs(U[:, :n1] - Uo[:, :n1]).max() <= 1e-12 * scale
+        np.testing.assert_allclose(lam[:n1], lamo[:n1], rtol=1e-14)
+        if U.shape[1] > n1:
+            P1, P2 = U[:, n1:] @ U[:, n1:].T, Uo[:, n1:] @ Uo[:, n1:].T
+            assert np.abs(P1 - P2).max() <= 1e-8 * np.abs(P2).max()
+            np.testing.assert_allclose(np.sort(lam[n1:]), np.sort(lamo[n1:]), rtol=1e-8)
