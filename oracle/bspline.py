@@ -74,7 +74,11 @@ def basis(knots: np.ndarray, p: int, x, der: int = 0) -> np.ndarray:
 
 
 def weight_values(weight, x):
-    """w(x) = c0 + c1*cos(a*x + b) (the weight family of the workloads)."""
+    """w(x) = c0 + c1*cos(a*x + b) (the weight family of the workloads), or
+    weight(x) for a callable weight (the separable approximations of
+    Appendix A)."""
+    if callable(weight):
+        return weight(np.asarray(x, dtype=float))
     c0, c1, a, b = weight
     return c0 + c1 * np.cos(a * x + b)
 
