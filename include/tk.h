@@ -90,6 +90,19 @@ tk_status tk_assemble_1d(int32_t n_el, int32_t p, int32_t kind, const double wei
 tk_status tk_assemble_1d_bc(int32_t n_el, int32_t p, int32_t kind, const double weight[4], int32_t k0,
                             int32_t k1, double* band);
 
+/* tk_assemble_1d_bc with the weight given as a Chebyshev series on [0, 1],
+ * w(x) = sum_{m < nc} c[m] T_m(2x - 1): the univariate integrals of
+ * Appendix A (eq. matrix_CP, a factor column of the separable approximation
+ * of an entry of Q), Gauss-Legendre exact for the polynomial integrand.
+ * EINVAL as tk_assemble_1d_bc or if nc is not in [1, 4096]. */
+tk_status tk_assemble_1d_cheb(int32_t n_el, int32_t p, int32_t kind, int32_t nc, const double* c, int32_t k0,
+                              int32_t k1, double* band);
+
+/* F_i = int b_i(x) w(x) dx on the space with flags (k0, k1), w a Chebyshev
+ * series as above (the rhs factors of Appendix A, F~_t). */
+tk_status tk_load_vector_1d_cheb(int32_t n_el, int32_t p, int32_t nc, const double* c, int32_t k0, int32_t k1,
+                                 double* F);
+
 /* Load vector F_i = int b_i(x) w(x) dx (host, caller-owned, n doubles). */
 tk_status tk_load_vector_1d(int32_t n_el, int32_t p, const double weight[4], double* F);
 

@@ -1211,6 +1211,30 @@ tk_status tk_assemble_1d_bc(int32_t n_el, int32_t p, int32_t kind, const double 
   return TK_OK;
 }
 
+tk_status tk_assemble_1d_cheb(int32_t n_el, int32_t p, int32_t kind, int32_t nc, const double* c, int32_t k0,
+                              int32_t k1, double* band) {
+  if (n_el < 1 || p < 1 || kind < 0 || kind > 3 || nc < 1 || nc > 4096 || !c || !band) return TK_EINVAL;
+  if ((k0 != 0 && k0 != 1) || (k1 != 0 && k1 != 1) || n_el + p - 2 + k0 + k1 < 1) return TK_EINVAL;
+  try {
+    assemble_band_cheb(n_el, p, kind, c, nc, band, k0, k1);
+  } catch (...) {
+    return TK_ENOMEM;
+  }
+  return TK_OK;
+}
+
+tk_status tk_load_vector_1d_cheb(int32_t n_el, int32_t p, int32_t nc, const double* c, int32_t k0, int32_t k1,
+                                 double* F) {
+  if (n_el < 1 || p < 1 || nc < 1 || nc > 4096 || !c || !F) return TK_EINVAL;
+  if ((k0 != 0 && k0 != 1) || (k1 != 0 && k1 != 1) || n_el + p - 2 + k0 + k1 < 1) return TK_EINVAL;
+  try {
+    load_vector_cheb(n_el, p, c, nc, F, k0, k1);
+  } catch (...) {
+    return TK_ENOMEM;
+  }
+  return TK_OK;
+}
+
 tk_status tk_load_vector_1d(int32_t n_el, int32_t p, const double weight[4], double* F) {
   if (n_el < 1 || p < 1 || !weight || !F || n_el + p - 2 < 1) return TK_EINVAL;
   try {

@@ -127,6 +127,76 @@ static inline double weight_at(const double w[4], double x) {
   return w[0] + w[1] * std::cos(w[2] * x + w[3]);
 }
 
+// w(x) = sum_m c[m] T_m(2x - 1) (three-term recurrence)
+static double cheb_weight(const double* c, int nc, double x) {
+  const double t = 2.0 * x - 1.0;
+  double t0 = 1.0, t1 = t, s = nc > 0 ? c[0] : 0.0;
+  if (nc > 1) s += c[1] * t1;
+  for (int m = 2; m < nc; ++m) {
+    const double t2 = 2.0 * t * t1 - t0;
+    s += c[m] * t2;
+    t0 = t1;
+    t1 = t2;
+  }
+  return s;
+}
+
+void assemble_band_cheb(int n_el, int p, int kind, const double* c, int nc, double* band, int k0, int k1) {
+  const int n = n_el + p - 2 + k0 + k1;
+  const int sh = 1 - k0;
+  const int nb = 2 * p + 1;
+  std::memset(band, 0, sizeof(double) * nb * n);
+  const auto kn = open_knots(n_el, p);
+  std::vector<double> gx, gw;
+  // exact for the polynomial weight of degree nc - 1 times the basis products
+  gauss_legendre(p + 1 + (nc + 1) / 2 + 2, gx, gw);
+  const int da = (kind == 1 || kind == 2) ? 1 : 0;
+  const int db = (kind == 1 || kind == 3) ? 1 : 0;
+  std::vector<double> vals(2 * (p + 1));
+  const double h = 1.0 / n_el;
+  for (int e = 0; e < n_el; ++e) {
+    const int span = e + p;
+    for (size_t q = 0; q < gx.size(); ++q) {
+      const double x = e * h + 0.5 * h * (gx[q] + 1.0);
+      const double wq = 0.5 * h * gw[q] * cheb_weight(c, nc, x);
+      span_basis(kn, p, span, x, 1, vals.data());
+      for (int a = 0; a <= p; ++a) {
+        const int i = span - p + a - sh;
+        if (i < 0 || i >= n) continue;
+        const double va = vals[da * (p + 1) + a];
+        for (int b = 0; b <= p; ++b) {
+          const int j = span - p + b - sh;
+          if (j < 0 || j >= n) continue;
+          band[(j - i + p) * n + i] += wq * va * vals[db * (p + 1) + b];
+        }
+      }
+    }
+  }
+}
+
+void load_vector_cheb(int n_el, int p, const double* c, int nc, double* F, int k0, int k1) {
+  const int n = n_el + p - 2 + k0 + k1;
+  const int sh = 1 - k0;
+  std::memset(F, 0, sizeof(double) * n);
+  const auto kn = open_knots(n_el, p);
+  std::vector<double> gx, gw;
+  gauss_legendre(p + 1 + (nc + 1) / 2 + 2, gx, gw);
+  std::vector<double> vals(p + 1);
+  const double h = 1.0 / n_el;
+  for (int e = 0; e < n_el; ++e) {
+    const int span = e + p;
+    for (size_t q = 0; q < gx.size(); ++q) {
+      const double x = e * h + 0.5 * h * (gx[q] + 1.0);
+      const double wq = 0.5 * h * gw[q] * cheb_weight(c, nc, x);
+      span_basis(kn, p, span, x, 0, vals.data());
+      for (int a = 0; a <= p; ++a) {
+        const int i = span - p + a - sh;
+        if (i >= 0 && i < n) F[i] += wq * vals[a];
+      }
+    }
+  }
+}
+
 void assemble_band(int n_el, int p, int kind, const double weight[4], double* band, int k0, int k1) {
   const int n = n_el + p - 2 + k0 + k1;
   const int sh = 1 - k0;  // full-basis index of space index 0

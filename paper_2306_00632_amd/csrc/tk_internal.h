@@ -38,6 +38,11 @@ void gauss_legendre(int nq, std::vector<double>& x, std::vector<double>& w);
 // kind: 0 mass, 1 stiffness, 2 mixed (d/dx on test function i), 3 mixed (trial j).
 void assemble_band(int n_el, int p, int kind, const double weight[4], double* band, int k0 = 0, int k1 = 0);
 
+// The same integrals with the weight w(x) = sum_{m < nc} c[m] T_m(2x - 1) (a
+// Chebyshev series on [0, 1], Appendix A), Gauss-Legendre exact for it.
+void assemble_band_cheb(int n_el, int p, int kind, const double* c, int nc, double* band, int k0, int k1);
+void load_vector_cheb(int n_el, int p, const double* c, int nc, double* F, int k0, int k1);
+
 // Dirichlet-space load vector F_i = int b_i g dx, g from the weight family.
 void load_vector(int n_el, int p, const double weight[4], double* F);
 

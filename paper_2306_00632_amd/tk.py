@@ -53,6 +53,8 @@ EXPORTS = {
     "tk_ctx_trim": (C.c_int32, [vp]),
     "tk_assemble_1d": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, dp, dp]),
     "tk_assemble_1d_bc": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, C.c_int32, dp]),
+    "tk_assemble_1d_cheb": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, C.c_int32, dp]),
+    "tk_load_vector_1d_cheb": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, C.c_int32, dp]),
     "tk_load_vector_1d": (C.c_int32, [C.c_int32, C.c_int32, dp, dp]),
     "tk_fd_direction_host": (C.c_int32, [C.c_int32, C.c_int32, C.c_double, i32p, i32p, i32p, dp, dp, dp, dp]),
     "tk_expsum_host": (C.c_int32, [C.c_double, C.c_double, i32p, dp, dp, dp, dp]),
@@ -141,6 +143,27 @@ def assemble_1d_bc(n_el: int, p: int, kind: str, weight=(1.0, 0.0, 0.0, 0.0), bc
     if st != TK_OK:
         raise TkError(st, "tk_assemble_1d_bc")
     return band
+
+
+def assemble_1d_cheb(n_el: int, p: int, kind: str, c, bc=(0, 0)) -> np.ndarray:
+    """DIA band (2p+1, n) with the weight sum_m c[m] T_m(2x - 1)."""
+    n = n_el + p - 2 + bc[0] + bc[1]
+    band = np.zeros((2 * p + 1, n))
+    cc = np.ascontiguousarray(c, dtype=np.float64)
+    st = lib().tk_assemble_1d_cheb(n_el, p, KINDS[kind], len(cc), _ptr(cc), int(bc[0]), int(bc[1]), _ptr(band))
+    if st != TK_OK:
+        raise TkError(st, "tk_assemble_1d_cheb")
+    return band
+
+
+def load_vector_1d_cheb(n_el: int, p: int, c, bc=(0, 0)) -> np.ndarray:
+    """F_i = int b_i(x) sum_m c[m] T_m(2x - 1) dx."""
+    F = np.zeros(n_el + p - 2 + bc[0] + bc[1])
+    cc = np.ascontiguousarray(c, dtype=np.float64)
+    st = lib().tk_load_vector_1d_cheb(n_el, p, len(cc), _ptr(cc), int(bc[0]), int(bc[1]), _ptr(F))
+    if st != TK_OK:
+        raise TkError(st, "tk_load_vector_1d_cheb")
+    return F
 
 
 def fd_direction_dense_host(n_el: int, p: int, coef: float = 1.0, bc=(0, 0)):

@@ -1,0 +1,115 @@
+"""GPU parity of the Appendix A front end (paper_2306_00632_amd/geometry.py:
+Chebyshev samples -> Tucker(values; Phi, Phi, Phi) -> tucker_truncate on the
+device -> 1D matrices and moments with Chebyshev-series weights) against
+the oracle's (oracle/frontend.py, pinned in test_oracle_frontend.py), on the
+thick quarter annulus with the manufactured solution of Sec. 5.1:
+* the Tucker matrix of eq. matrix_CP: the ranks of the separable Q entries
+  ((1, 1, 1) on the diagonal, none off it, as the paper reports for this
+  domain) and the operator applied to a random Tucker tensor (1e-10);
+* the right-hand side: the two truncations of the same coefficient tensor
+  each discard at most eps * scale, so the full vectors differ by at most
+  2 eps scale ||B||_2^3 with B[i, m] = int b_i T_m(2x - 1) (checked with a
+  10% margin for rounding);
+* TPCG on that system against the oracle's sparse direct solve of the
+  oracle's system (1e-6), and the error to the manufactured solution
+  falling under refinement as the oracle's does.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bspline
+from oracle import frontend as fe
+from oracle import tucker as T
+
+from gpu_helpers import context, rel, say, to_oracle, to_oracle_plain
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return context()
+
+
+@pytest.mark.parametrize("n_el,p", [(6, 2), (5, 3)])
+def test_operator_parity(ctx, n_el, p):
+    from paper_2306_00632_amd import geometry, tk
+    t, eps = 17, 1e-10
+    say(f"front end operator n_el={n_el} p={p} t={t}")
+    q, _, _ = W.annulus_samples(t)
+    op, ranks = geometry.operator(ctx, n_el, p, q, eps)
+    op_o, ranks_o = fe.operator(n_el, p, fe.annulus_jacobian, t, eps)
+    for k in range(3):
+        for l in range(3):
+            assert tuple(ranks[(k, l)]) == ((1, 1, 1) if k == l else (0, 0, 0)), (k, l, ranks[(k, l)])
+    assert ranks_o == {kl: tuple(r) for kl, r in ranks.items()}
+    n = n_el + p - 2
+    core, U = W.random_tucker((n, n, n), (3, 2, 4), 7)
+    y = to_oracle(tk.tucker_apply_op(ctx, op, tk.Tucker.from_host(ctx, core, U))).full()
+    ref = T.apply_op(op_o, T.Tucker(core, U)).full()
+    err = rel(y, ref)
+    say(f"   rel={err:.2e}")
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-9])
+def test_rhs_parity(ctx, eps):
+    from paper_2306_00632_amd import geometry
+    n_el, p, t = 8, 2, 40
+    say(f"front end rhs eps={eps:g} t={t}")
+    _, omega, _ = W.annulus_samples(t)
+    f = to_oracle_plain(geometry.rhs(ctx, n_el, p, omega, eps)).full()
+    g = fe.rhs(n_el, p, fe.annulus_omega, t, eps)
+    ref = g.full()
+    scale = float(np.abs(omega).max())
+    nq = fe.exact_nq(p, t)
+    B = np.stack([bspline.load_vector(n_el, p, lambda x, m=m: fe.cheb_eval(np.eye(t)[m], x), nq=nq)
+                  for m in range(t)], axis=1)
+    bound = 1.1 * 2.0 * eps * scale * np.linalg.norm(B, 2) ** 3
+    diff = float(np.linalg.norm(f - ref))
+    say(f"   |f - f_oracle| = {diff:.2e}, bound {bound:.2e}, |f| = {np.linalg.norm(ref):.2e}")
+    assert diff <= bound
+    assert bound < 1e-3 * np.linalg.norm(ref)   # the bound is informative
+
+
+def _oracle_solution(n_el, p, t_op, t_rhs, eps):
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    op, _ = fe.operator(n_el, p, fe.annulus_jacobian, t_op, eps)
+    f = fe.rhs(n_el, p, fe.annulus_omega, t_rhs, eps)
+    n = n_el + p - 2
+    A = sum(c * sp.kron(sp.csr_matrix(op.mats[2][i3]), sp.kron(sp.csr_matrix(op.mats[1][i2]),
+                                                                sp.csr_matrix(op.mats[0][i1])))
+            for i1, i2, i3, c in op.nnz)
+    return spla.spsolve(A.tocsc(), f.full().reshape(-1, order="F")).reshape((n, n, n), order="F")
+
+
+def _error_to_manufactured(X, n_el, p, u):
+    e = np.linspace(0.05, 0.95, 9)
+    E1, E2, E3 = np.meshgrid(e, e, e, indexing="ij")
+    Bs = bspline.dirichlet_basis_at(n_el, p, e)
+    uh = np.einsum("abc,ia,jb,kc->ijk", X, Bs, Bs, Bs)
+    ue = u(*fe.annulus_map(E1, E2, E3))
+    return float(np.abs(uh - ue).max() / np.abs(ue).max())
+
+
+def test_tpcg_annulus_against_direct_and_manufactured(ctx):
+    from paper_2306_00632_amd import geometry, tk
+    p, t_op, t_rhs, eps = 2, 33, 64, 1e-10
+    q, _, u = W.annulus_samples(t_op)
+    _, omega, _ = W.annulus_samples(t_rhs)
+    errs = []
+    for n_el in (8, 16):
+        say(f"front end tpcg annulus n_el={n_el} p={p}")
+        op, _ = geometry.operator(ctx, n_el, p, q, eps)
+        f = geometry.rhs(ctx, n_el, p, omega, eps)
+        P = tk.Preconditioner.create(ctx, n_el, p, 0.1, geometry.fd_coefficients(q))
+        x, info = tk.tpcg_solve(ctx, op, P, f, tol=1e-10)
+        X = to_oracle_plain(x).full()
+        err = rel(X, _oracle_solution(n_el, p, t_op, t_rhs, eps))
+        errs.append(_error_to_manufactured(X, n_el, p, u))
+        say(f"   iters={info['iters']} rank={info['rank']} rel_vs_direct={err:.2e} err_u={errs[-1]:.3e}")
+        assert info["converged"]
+        assert err <= 1e-6
+    assert errs[1] < errs[0] / 4 and errs[1] < 0.1, errs

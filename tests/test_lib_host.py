@@ -164,3 +164,26 @@ def test_fd_direction_dense_matches_oracle(bc, p):
             P1, P2 = U[:, n1:] @ U[:, n1:].T, Uo[:, n1:] @ Uo[:, n1:].T
             assert np.abs(P1 - P2).max() <= 1e-8 * np.abs(P2).max()
             np.testing.assert_allclose(np.sort(lam[n1:]), np.sort(lamo[n1:]), rtol=1e-8)
+
+
+@pytest.mark.parametrize("bc", [(0, 0), (1, 0)])
+@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("nc", [1, 6, 17])
+def test_assemble_1d_cheb_matches_oracle(bc, p, nc):
+    """tk_assemble_1d_cheb / tk_load_vector_1d_cheb (Appendix A: weights that
+    are Chebyshev series on [0, 1]) against the oracle's matrices and moments
+    with the series as a callable weight and a Gauss rule exact for it
+    (elementwise 1e-13 of the largest entry)."""
+    from oracle import bspline
+    from oracle import frontend as fe
+    from paper_2306_00632_amd import tk
+    c = np.random.default_rng(nc + 10 * p).standard_normal(nc) / (1.0 + np.arange(nc))
+    w = lambda x: fe.cheb_eval(c, x)
+    nq = fe.exact_nq(p, nc)
+    for kind in ("mass", "stiff", "mixed10", "mixed01"):
+        A = band_dense(tk.assemble_1d_cheb(9, p, kind, c, bc), p)
+        ref = bspline.matrix(9, p, kind, w, nq=nq, bc=bc)
+        assert np.abs(A - ref).max() <= 1e-13 * np.abs(ref).max(), kind
+    F = tk.load_vector_1d_cheb(9, p, c, bc)
+    Fo = bspline.load_vector(9, p, w, nq=nq, bc=bc)
+    assert np.abs(F - Fo).max() <= 1e-13 * np.abs(Fo).max()

@@ -233,3 +233,37 @@ def config_elasticity() -> BlockWorkload:
     w = elasticity(256, 3, 1.0, 0.5, 4, 5002, 5003, name="elasticity_p3_nel256_r4")
     w.eps_min = 1e-8
     return w
+
+
+# --- Appendix A inputs: geometry coefficients sampled on a Chebyshev grid -----
+
+def annulus_samples(t: int) -> tuple:
+    """Samples, on the tensor grid of t Chebyshev-Lobatto points of [0, 1]^3
+    (x_k = (1 + cos(pi k / (t - 1))) / 2), of the thick quarter annulus
+    F(eta) = ((1 + eta_1) cos(pi eta_2 / 2), (1 + eta_1) sin(pi eta_2 / 2), eta_3):
+    q[(k, l)] the entries of det(J) J^-1 J^-T, here diag(pi r / 2, 2 / (pi r),
+    pi r / 2) with r = 1 + eta_1 (zero off the diagonal), and omega =
+    det(J) f(F(eta)) for f = -Laplace u, u = (rho^2 - 1)(rho^2 - 4) sin(pi z)
+    sin(7 x y), which vanishes on the boundary (the manufactured solution of
+    Sec. 5.1).  Returns (q, omega, u) with u the solution as a function of
+    physical coordinates."""
+    x = 0.5 * (1.0 + np.cos(np.pi * np.arange(t) / (t - 1)))
+    E1, E2, E3 = np.meshgrid(x, x, x, indexing="ij")
+    r, th = 1.0 + E1, 0.5 * np.pi * E2
+    q = {(k, l): np.zeros((t, t, t)) for k in range(3) for l in range(3)}
+    q[(0, 0)] = 0.5 * np.pi * r
+    q[(1, 1)] = 2.0 / (np.pi * r)
+    q[(2, 2)] = 0.5 * np.pi * r
+    X, Y, Z = r * np.cos(th), r * np.sin(th), E3
+    rho2 = X * X + Y * Y
+    g = (rho2 - 1.0) * (rho2 - 4.0)
+    sn, cs, sz = np.sin(7.0 * X * Y), np.cos(7.0 * X * Y), np.sin(np.pi * Z)
+    # Laplace of g * sin(7xy) in the plane: (16 rho^2 - 20) sn + 2 grad g . grad sn + g (-49 rho^2 sn)
+    lap_xy = (16.0 * rho2 - 20.0) * sn + 28.0 * (4.0 * rho2 - 10.0) * X * Y * cs - 49.0 * rho2 * g * sn
+    f = -(sz * lap_xy - np.pi ** 2 * g * sn * sz)
+    omega = 0.5 * np.pi * r * f
+
+    def u(X, Y, Z):
+        rho2 = X * X + Y * Y
+        return (rho2 - 1.0) * (rho2 - 4.0) * np.sin(np.pi * Z) * np.sin(7.0 * X * Y)
+    return q, omega, u
