@@ -41,7 +41,7 @@ Prints one JSON line (see the "metric" key) with:
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload deformed|small]
                        [--fd approx|exact] [--arith f64|mixed] [--no-hbm] [--no-serve]
-                       [--no-bc] [--serve-slots S] [--no-cpu-baseline]
+                       [--no-bc] [--no-annulus] [--serve-slots S] [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -268,6 +268,69 @@ def boundary_conditions(ctx, reps=3):
     return out
 
 
+def annulus(ctx, p_list=(2, 3, 4, 5), n_el_list=(128, 256, 512, 1024), scaled_p=(3,), manufactured=True):
+    """Sec. 5.1's thick quarter annulus through the Appendix A front end:
+    Q and omega sampled on Chebyshev-Lobatto grids (t = 33 and 64 points per
+    direction), their coefficient tensors truncated on the device to the
+    paper's eps = max(tol / 10, 1e-12), the 1D matrices and moments of the
+    factor columns assembled on the host, and TPCG at tol = 1e-6 with
+    eps_prec = 0.1.  Per (p, n_el): the iterations (the paper's table for
+    this domain reports 12 everywhere), the solution rank, the front-end,
+    FD-setup and solve times, with the FD of the parametric Laplacian (eq.
+    FD_prec with unit coefficients) and, for p in scaled_p, with the mean of
+    each diagonal entry of Q as direction coefficient.  With
+    manufactured=True, a solve at n_el = 128, p = 3, tol = 1e-10 gives the
+    error to the manufactured solution on a 9^3 grid of parametric points
+    (max-norm, relative)."""
+    import numpy as np
+    from paper_2306_00632_amd import geometry, tk
+    import workloads as W
+    tol, t_q, t_w = 1e-6, 33, 64
+    eps = max(0.1 * tol, 1e-12)
+    q, _, u = W.annulus_samples(t_q)
+    _, omega, _ = W.annulus_samples(t_w)
+    coef = geometry.fd_coefficients(q)
+    out = {"tol": tol, "eps_front_end": eps, "t_q": t_q, "t_omega": t_w, "eps_prec": 0.1,
+           "paper_iterations": 12, "scaled_fd_coefficients": list(coef), "runs": []}
+    for p in p_list:
+        for n_el in n_el_list:
+            ctx.sync()
+            t0 = time.perf_counter()
+            op, ranks = geometry.operator(ctx, n_el, p, q, eps)
+            f = geometry.rhs(ctx, n_el, p, omega, eps)
+            ctx.sync()
+            t1 = time.perf_counter()
+            for fd, c in (("parametric", (1.0, 1.0, 1.0)), ("scaled", coef)):
+                if fd == "scaled" and p not in scaled_p:
+                    continue
+                ctx.sync()
+                t2 = time.perf_counter()
+                P = tk.Preconditioner.create(ctx, n_el, p, 0.1, c)
+                ctx.sync()
+                t3 = time.perf_counter()
+                x, info = tk.tpcg_solve(ctx, op, P, f, tol=tol)
+                ctx.sync()
+                t4 = time.perf_counter()
+                out["runs"].append({"p": p, "n_el": n_el, "fd": fd, "iters": info["iters"],
+                                    "relres": info["relres"], "rank": list(info["rank"]),
+                                    "rhs_rank": list(f.shape()[1]), "front_end_ms": 1e3 * (t1 - t0),
+                                    "fd_setup_ms": 1e3 * (t3 - t2), "solve_ms": 1e3 * (t4 - t3)})
+    if manufactured:
+        n_el, p = 128, 3
+        op, _ = geometry.operator(ctx, n_el, p, q, 1e-11)
+        f = geometry.rhs(ctx, n_el, p, omega, 1e-11)
+        x, info = tk.tpcg_solve(ctx, op, tk.Preconditioner.create(ctx, n_el, p, 0.1, coef), f, tol=1e-10)
+        e = np.linspace(0.05, 0.95, 9)
+        E1, E2, E3 = np.meshgrid(e, e, e, indexing="ij")
+        r, th = 1.0 + E1, 0.5 * np.pi * E2
+        ue = u(r * np.cos(th), r * np.sin(th), E3)
+        uh = geometry.evaluate(x, n_el, p, e, e, e)
+        out["manufactured"] = {"n_el": n_el, "p": p, "tol": 1e-10, "fd": "scaled", "iters": info["iters"],
+                               "rank": list(info["rank"]),
+                               "max_rel_err": float(np.abs(uh - ue).max() / np.abs(ue).max())}
+    return out
+
+
 def matrix_cores(ctx, solve_kernels, reps=5):
     """FP64 matrix-core rates: a square GEMM of order 4096 through the
     library's own DGEMM (tk_dgemm, the kernel of every dense contraction of
@@ -381,6 +444,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
     ap.add_argument("--no-bc", action="store_true",
                     help="skip the solves with Neumann ends and non-homogeneous Dirichlet data")
+    ap.add_argument("--no-annulus", action="store_true",
+                    help="skip the thick quarter annulus solves through the Appendix A front end")
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--fd", choices=("approx", "exact"), default="approx",
                     help="preconditioner eigenpairs: Appendix B approximations applied by sine transforms "
@@ -503,6 +568,8 @@ def main():
         out["matrix_cores"] = matrix_cores(ctx, kernels)
     if not args.no_bc:
         out["boundary_conditions"] = boundary_conditions(ctx)
+    if not args.no_annulus:
+        out["annulus"] = annulus(ctx)
     if not args.no_serve:
         out["serving"] = serving(args.serve_slots)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:

@@ -103,6 +103,15 @@ tk_status tk_assemble_1d_cheb(int32_t n_el, int32_t p, int32_t kind, int32_t nc,
 tk_status tk_load_vector_1d_cheb(int32_t n_el, int32_t p, int32_t nc, const double* c, int32_t k0, int32_t k1,
                                  double* F);
 
+/* Values (der = 0) or derivatives (der <= p) of the n = n_el + p - 2 + k0 + k1
+ * B-splines of the space with flags (k0, k1) (Sec. 2.1-2.2) at npts points
+ * x in [0, 1]: out (npts x n, column-major, caller-owned; host).  A solution
+ * with Tucker factors U_k is evaluated at a tensor grid of points as its
+ * core times (B_k U_k) in each mode.  EINVAL on bad flags, der > p or a
+ * point outside [0, 1]. */
+tk_status tk_basis_values_1d(int32_t n_el, int32_t p, int32_t k0, int32_t k1, int32_t der, int64_t npts,
+                             const double* x, double* out);
+
 /* Load vector F_i = int b_i(x) w(x) dx (host, caller-owned, n doubles). */
 tk_status tk_load_vector_1d(int32_t n_el, int32_t p, const double weight[4], double* F);
 

@@ -1235,6 +1235,21 @@ tk_status tk_load_vector_1d_cheb(int32_t n_el, int32_t p, int32_t nc, const doub
   return TK_OK;
 }
 
+tk_status tk_basis_values_1d(int32_t n_el, int32_t p, int32_t k0, int32_t k1, int32_t der, int64_t npts,
+                             const double* x, double* out) {
+  if (n_el < 1 || p < 1 || der < 0 || der > p || npts < 0 || (npts > 0 && (!x || !out))) return TK_EINVAL;
+  if ((k0 != 0 && k0 != 1) || (k1 != 0 && k1 != 1) || n_el + p - 2 + k0 + k1 < 1) return TK_EINVAL;
+  for (int64_t q = 0; q < npts; ++q)
+    if (!(x[q] >= 0.0 && x[q] <= 1.0)) return TK_EINVAL;
+  if (npts > INT32_MAX) return TK_EINVAL;
+  try {
+    basis_values(n_el, p, k0, k1, der, int(npts), x, out);
+  } catch (...) {
+    return TK_ENOMEM;
+  }
+  return TK_OK;
+}
+
 tk_status tk_load_vector_1d(int32_t n_el, int32_t p, const double weight[4], double* F) {
   if (n_el < 1 || p < 1 || !weight || !F || n_el + p - 2 < 1) return TK_EINVAL;
   try {

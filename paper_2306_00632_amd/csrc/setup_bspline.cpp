@@ -253,6 +253,22 @@ void load_vector(int n_el, int p, const double weight[4], double* F) {
   }
 }
 
+void basis_values(int n_el, int p, int k0, int k1, int der, int npts, const double* x, double* out) {
+  const int n = n_el + p - 2 + k0 + k1;
+  const int sh = 1 - k0;
+  std::memset(out, 0, sizeof(double) * size_t(npts) * n);
+  const auto kn = open_knots(n_el, p);
+  std::vector<double> tmp((der + 1) * (p + 1));
+  for (int q = 0; q < npts; ++q) {
+    const int span = find_span(kn, p, x[q]);
+    span_basis(kn, p, span, x[q], der, tmp.data());
+    for (int a = 0; a <= p; ++a) {
+      const int i = span - p + a - sh;
+      if (i >= 0 && i < n) out[q + size_t(npts) * i] = tmp[der * (p + 1) + a];
+    }
+  }
+}
+
 void dirichlet_basis_at(int n_el, int p, double x, int der, double* vals) {
   const int n = n_el + p - 2;
   for (int i = 0; i < n; ++i) vals[i] = 0.0;

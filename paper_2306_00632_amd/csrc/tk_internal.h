@@ -46,6 +46,11 @@ void load_vector_cheb(int n_el, int p, const double* c, int nc, double* F, int k
 // Dirichlet-space load vector F_i = int b_i g dx, g from the weight family.
 void load_vector(int n_el, int p, const double weight[4], double* F);
 
+// Derivative `der` of the n = n_el + p - 2 + k0 + k1 basis functions of the
+// space with flags (k0, k1) at npts points x in [0, 1]: out (npts x n,
+// column-major).
+void basis_values(int n_el, int p, int k0, int k1, int der, int npts, const double* x, double* out);
+
 // Dirichlet basis (n = n_el + p - 2 functions) derivative `der` at x.
 void dirichlet_basis_at(int n_el, int p, double x, int der, double* vals);
 

@@ -107,3 +107,12 @@ def fd_coefficients(q_values) -> tuple:
     of Q, i.e. the parametric Laplacian scaled to the geometry's average
     anisotropy."""
     return tuple(float(np.mean(q_values[(k, k)])) for k in range(3))
+
+
+def evaluate(x: "tk.Tucker", n_el: int, p: int, e1, e2, e3, bc=((0, 0),) * 3) -> np.ndarray:
+    """The spline function with Tucker coefficients x on the tensor grid
+    e1 x e2 x e3 of parametric points: core x_k (B_k U_k), B_k the basis
+    values from tk_basis_values_1d (host post-processing)."""
+    core, U = x.plain()
+    V = [tk.basis_values_1d(n_el, p, e, 0, bc[k]) @ U[k] for k, e in enumerate((e1, e2, e3))]
+    return np.einsum("abc,ia,jb,kc->ijk", core, V[0], V[1], V[2])

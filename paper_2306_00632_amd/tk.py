@@ -55,6 +55,7 @@ EXPORTS = {
     "tk_assemble_1d_bc": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, C.c_int32, dp]),
     "tk_assemble_1d_cheb": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, C.c_int32, dp]),
     "tk_load_vector_1d_cheb": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, C.c_int32, dp]),
+    "tk_basis_values_1d": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64, dp, dp]),
     "tk_load_vector_1d": (C.c_int32, [C.c_int32, C.c_int32, dp, dp]),
     "tk_fd_direction_host": (C.c_int32, [C.c_int32, C.c_int32, C.c_double, i32p, i32p, i32p, dp, dp, dp, dp]),
     "tk_expsum_host": (C.c_int32, [C.c_double, C.c_double, i32p, dp, dp, dp, dp]),
@@ -164,6 +165,18 @@ def load_vector_1d_cheb(n_el: int, p: int, c, bc=(0, 0)) -> np.ndarray:
     if st != TK_OK:
         raise TkError(st, "tk_load_vector_1d_cheb")
     return F
+
+
+def basis_values_1d(n_el: int, p: int, x, der: int = 0, bc=(0, 0)) -> np.ndarray:
+    """(len(x), n) values (or derivatives) of the basis of the space with flags bc."""
+    xx = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    n = n_el + p - 2 + bc[0] + bc[1]
+    out = np.zeros((xx.size, n), order="F")
+    st = lib().tk_basis_values_1d(n_el, p, int(bc[0]), int(bc[1]), der, xx.size, _ptr(xx),
+                                  out.ctypes.data_as(dp))
+    if st != TK_OK:
+        raise TkError(st, "tk_basis_values_1d")
+    return out
 
 
 def fd_direction_dense_host(n_el: int, p: int, coef: float = 1.0, bc=(0, 0)):

@@ -113,3 +113,28 @@ def test_tpcg_annulus_against_direct_and_manufactured(ctx):
         assert info["converged"]
         assert err <= 1e-6
     assert errs[1] < errs[0] / 4 and errs[1] < 0.1, errs
+
+
+@pytest.mark.parametrize("p", [2, 4])
+def test_tpcg_annulus_iterations_are_robust(ctx, p):
+    """Sec. 5.1's robustness test at tol = 1e-6 (front-end eps = tol / 10):
+    with the FD scaled by the mean diagonal of Q the iteration count is at
+    most the paper's 12 and the same (within 1) at n_el = 64 and 128; with
+    the FD of the unit-coefficient parametric Laplacian, whose P^-1 A has
+    its spectrum in [min Q_kk, max Q_kk] (condition about 10 for this map),
+    it stays below 26 (measured 20-23 up to n_el = 1024, p = 2-5)."""
+    from paper_2306_00632_amd import geometry, tk
+    q, _, _ = W.annulus_samples(33)
+    _, omega, _ = W.annulus_samples(64)
+    coef = geometry.fd_coefficients(q)
+    its = {}
+    for n_el in (64, 128):
+        op, _ = geometry.operator(ctx, n_el, p, q, 1e-7)
+        f = geometry.rhs(ctx, n_el, p, omega, 1e-7)
+        for name, c in (("scaled", coef), ("parametric", (1.0, 1.0, 1.0))):
+            x, info = tk.tpcg_solve(ctx, op, tk.Preconditioner.create(ctx, n_el, p, 0.1, c), f, tol=1e-6)
+            assert info["converged"]
+            its[(name, n_el)] = info["iters"]
+    say(f"annulus p={p} iterations {its}")
+    assert its[("scaled", 128)] <= 12 and abs(its[("scaled", 128)] - its[("scaled", 64)]) <= 1
+    assert its[("parametric", 128)] < 26

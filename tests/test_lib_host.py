@@ -187,3 +187,23 @@ def test_assemble_1d_cheb_matches_oracle(bc, p, nc):
     F = tk.load_vector_1d_cheb(9, p, c, bc)
     Fo = bspline.load_vector(9, p, w, nq=nq, bc=bc)
     assert np.abs(F - Fo).max() <= 1e-13 * np.abs(Fo).max()
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_basis_values_1d_matches_oracle(bc, p):
+    """tk_basis_values_1d against the oracle's B-splines restricted to the
+    space with flags bc, values and first derivatives, including the ends
+    and interior knots (1e-13); a point outside [0, 1] is rejected."""
+    from oracle import bspline
+    from paper_2306_00632_amd import tk
+    n_el = 7
+    x = np.concatenate([[0.0, 1.0, 3.0 / 7.0], np.random.default_rng(p).uniform(0, 1, 30)])
+    lo, hi = bspline.dof_range(n_el, p, bc)
+    kn = bspline.open_knots(n_el, p)
+    for der in (0, 1):
+        B = tk.basis_values_1d(n_el, p, x, der, bc)
+        ref = bspline.basis(kn, p, x, der)[:, lo:hi]
+        assert np.abs(B - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), der
+    with pytest.raises(tk.TkError):
+        tk.basis_values_1d(n_el, p, [1.5], 0, bc)
