@@ -268,30 +268,39 @@ def boundary_conditions(ctx, reps=3):
     return out
 
 
-def annulus(ctx, p_list=(2, 3, 4, 5), n_el_list=(128, 256, 512, 1024), scaled_p=(3,), manufactured=True):
-    """Sec. 5.1's thick quarter annulus through the Appendix A front end:
-    Q and omega sampled on Chebyshev-Lobatto grids (t = 33 and 64 points per
+def mapped_domain(ctx, domain="annulus", p_list=(2, 3, 4, 5), n_el_list=(128, 256, 512, 1024), scaled_p=(3,),
+                  manufactured=True):
+    """Sec. 5.1-5.2's mapped domains through the Appendix A front end: the
+    thick quarter annulus with the manufactured solution, or the stand-in
+    spherical shell (a gnomonic patch, radii 1 and 2) with f = 1.  Q and
+    omega are sampled on Chebyshev-Lobatto grids (t = 33 and 64 points per
     direction), their coefficient tensors truncated on the device to the
     paper's eps = max(tol / 10, 1e-12), the 1D matrices and moments of the
-    factor columns assembled on the host, and TPCG at tol = 1e-6 with
-    eps_prec = 0.1.  Per (p, n_el): the iterations (the paper's table for
-    this domain reports 12 everywhere), the solution rank, the front-end,
-    FD-setup and solve times, with the FD of the parametric Laplacian (eq.
-    FD_prec with unit coefficients) and, for p in scaled_p, with the mean of
-    each diagonal entry of Q as direction coefficient.  With
-    manufactured=True, a solve at n_el = 128, p = 3, tol = 1e-10 gives the
-    error to the manufactured solution on a 9^3 grid of parametric points
-    (max-norm, relative)."""
+    factor columns assembled on the host, and TPCG run at tol = 1e-6 with
+    eps_prec = 0.1.  Per (p, n_el): the iterations (the paper's tables
+    report 12 everywhere for the annulus and 74-106 for its shell), the
+    solution rank, the front-end, FD-setup and solve times, with the FD of
+    the parametric Laplacian (eq. FD_prec with unit coefficients) and, for p
+    in scaled_p, with the mean of each diagonal entry of Q as direction
+    coefficient.  For the annulus with manufactured=True, a solve at
+    n_el = 128, p = 3, tol = 1e-10 gives the error to the manufactured
+    solution on a 9^3 grid of parametric points (max-norm, relative)."""
     import numpy as np
     from paper_2306_00632_amd import geometry, tk
     import workloads as W
     tol, t_q, t_w = 1e-6, 33, 64
     eps = max(0.1 * tol, 1e-12)
-    q, _, u = W.annulus_samples(t_q)
-    _, omega, _ = W.annulus_samples(t_w)
+    if domain == "annulus":
+        q, _, u = W.annulus_samples(t_q)
+        _, omega, _ = W.annulus_samples(t_w)
+        paper_iters = "12 for every p and n_el"
+    else:
+        q, _ = W.shell_samples(t_q)
+        _, omega = W.shell_samples(t_w)
+        paper_iters = "74-106 (the paper's shell map is not given; this one is a stand-in)"
     coef = geometry.fd_coefficients(q)
     out = {"tol": tol, "eps_front_end": eps, "t_q": t_q, "t_omega": t_w, "eps_prec": 0.1,
-           "paper_iterations": 12, "scaled_fd_coefficients": list(coef), "runs": []}
+           "paper_iterations": paper_iters, "scaled_fd_coefficients": list(coef), "runs": []}
     for p in p_list:
         for n_el in n_el_list:
             ctx.sync()
@@ -300,6 +309,7 @@ def annulus(ctx, p_list=(2, 3, 4, 5), n_el_list=(128, 256, 512, 1024), scaled_p=
             f = geometry.rhs(ctx, n_el, p, omega, eps)
             ctx.sync()
             t1 = time.perf_counter()
+            out.setdefault("q_ranks", {f"{k + 1}{l + 1}": list(r) for (k, l), r in ranks.items()})
             for fd, c in (("parametric", (1.0, 1.0, 1.0)), ("scaled", coef)):
                 if fd == "scaled" and p not in scaled_p:
                     continue
@@ -315,7 +325,7 @@ def annulus(ctx, p_list=(2, 3, 4, 5), n_el_list=(128, 256, 512, 1024), scaled_p=
                                     "relres": info["relres"], "rank": list(info["rank"]),
                                     "rhs_rank": list(f.shape()[1]), "front_end_ms": 1e3 * (t1 - t0),
                                     "fd_setup_ms": 1e3 * (t3 - t2), "solve_ms": 1e3 * (t4 - t3)})
-    if manufactured:
+    if manufactured and domain == "annulus":
         n_el, p = 128, 3
         op, _ = geometry.operator(ctx, n_el, p, q, 1e-11)
         f = geometry.rhs(ctx, n_el, p, omega, 1e-11)
@@ -445,7 +455,7 @@ def main():
     ap.add_argument("--no-bc", action="store_true",
                     help="skip the solves with Neumann ends and non-homogeneous Dirichlet data")
     ap.add_argument("--no-annulus", action="store_true",
-                    help="skip the thick quarter annulus solves through the Appendix A front end")
+                    help="skip the thick quarter annulus and spherical shell solves through the Appendix A front end")
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--fd", choices=("approx", "exact"), default="approx",
                     help="preconditioner eigenpairs: Appendix B approximations applied by sine transforms "
@@ -489,6 +499,7 @@ def main():
 
     # timed solves, uninstrumented
     times = []
+    refinements0 = ctx.truncate_refinements()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
@@ -500,6 +511,7 @@ def main():
         del x
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
+    refinements = (ctx.truncate_refinements() - refinements0) / max(args.steps, 1)
     # one more solve with HIP events around every launch: per-family kernel
     # times for the breakdown and the roofline (not part of the timed value)
     ctx.prof(True)
@@ -555,7 +567,8 @@ def main():
                    "dofs_per_direction": w.n,
                    "kronecker_terms": len(w.nnz), "rhs_rank": int(np.asarray(problem.rhs_arrays(w)[0]).shape[0]),
                    "tol": w.tol, "iters": last_info["iters"], "relres": last_info["relres"],
-                   "solution_rank": list(last_info["rank"]), "trel_calls": last_info["trel_calls"]},
+                   "solution_rank": list(last_info["rank"]), "trel_calls": last_info["trel_calls"],
+                   "tail_refinements_per_solve": refinements},
         "latency_ms": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99)),
                        "min": min(ms), "max": max(ms)},
         "mode_product_GB_s": mode_gbs,
@@ -569,7 +582,8 @@ def main():
     if not args.no_bc:
         out["boundary_conditions"] = boundary_conditions(ctx)
     if not args.no_annulus:
-        out["annulus"] = annulus(ctx)
+        out["annulus"] = mapped_domain(ctx, "annulus")
+        out["shell"] = mapped_domain(ctx, "shell")
     if not args.no_serve:
         out["serving"] = serving(args.serve_slots)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:

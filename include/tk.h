@@ -335,6 +335,11 @@ typedef struct {
                       the x update, the residual f - A x, scalar products and
                       truncations stay FP64 (the residual is recomputed from x,
                       so the FP32 steps change the search directions only) */
+  double refine_below; /* truncations with a relative tolerance below this refine
+                          the unresolved tail of each ST-HOSVD mode by a second
+                          eigendecomposition (tk_truncate_refinements); above
+                          it the Gram eigenvectors alone decide the ranks, which
+                          may then exceed the SVD-based ones (1e-8) */
 } tk_tpcg_params;
 
 enum { TK_ARITH_MIXED = 2 };
@@ -361,6 +366,13 @@ tk_status tk_prof_reset(tk_ctx* ctx);
  * one family since the last reset (synchronises). */
 tk_status tk_prof_read(tk_ctx* ctx, int32_t kind, int64_t* launches, double* ms, double* bytes,
                        double* flops);
+
+/* Number of ST-HOSVD modes, over the context's life, whose rank cut fell
+ * among directions that the mode's Gram matrix does not resolve (energies
+ * below about 64 a eps_mach times the mode's energy) and that were refined by
+ * a second eigendecomposition of the remaining coordinates (tucker_truncate
+ * and every truncation inside the solvers).  Host only. */
+tk_status tk_truncate_refinements(const tk_ctx* ctx, int64_t* count);
 
 /* Fill `p` with the defaults of Sec. 5. */
 void tk_tpcg_defaults(tk_tpcg_params* p);

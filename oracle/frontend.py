@@ -19,7 +19,10 @@ Readings (listed in DESIGN.md):
 * Chebyshev polynomials are those of [0, 1]: T_m(2 eta - 1);
 * stand-in geometries of the experiments (their maps are given as figures
   only): the thick quarter annulus F(eta) = ((1 + eta_1) cos(pi eta_2 / 2),
-  (1 + eta_1) sin(pi eta_2 / 2), eta_3) (radii 1 and 2, height 1).
+  (1 + eta_1) sin(pi eta_2 / 2), eta_3) (radii 1 and 2, height 1), and a
+  piece of a spherical shell (radii 1 and 2) over a gnomonic patch,
+  F(eta) = (1 + eta_1) w / |w| with w = (1, eta_2, eta_3), a map that is not
+  orthogonal (Q_23 != 0) and not a tensor product, with the load f = 1.
 """
 from __future__ import annotations
 
@@ -143,6 +146,36 @@ def annulus_omega(e1, e2, e3):
     """omega = det(J) f(F(eta))."""
     J = annulus_jacobian(e1, e2, e3)
     return np.linalg.det(J) * annulus_load(*annulus_map(e1, e2, e3))
+
+
+# ---------------------------------------------------------------------------
+# the spherical-shell piece (gnomonic patch)
+# ---------------------------------------------------------------------------
+
+def shell_map(e1, e2, e3):
+    rho = 1.0 + e1
+    nw = np.sqrt(1.0 + e2 * e2 + e3 * e3)
+    return rho / nw, rho * e2 / nw, rho * e3 / nw
+
+
+def shell_jacobian(e1, e2, e3):
+    """J[..., a, b] = d F_a / d eta_b: the radial column is the unit vector
+    S = w / |w|; d S / d eta_2 = (e_y - S S_y) / |w|, likewise for eta_3."""
+    rho = 1.0 + e1
+    nw = np.sqrt(1.0 + e2 * e2 + e3 * e3)
+    S = np.stack([1.0 / nw, e2 / nw, e3 / nw], axis=-1)
+    J = np.zeros(np.shape(e1) + (3, 3))
+    J[..., :, 0] = S
+    for b, comp in ((1, 1), (2, 2)):
+        col = -S * S[..., comp:comp + 1]
+        col[..., comp] += 1.0
+        J[..., :, b] = rho[..., None] * col / nw[..., None]
+    return J
+
+
+def shell_omega(e1, e2, e3):
+    """omega = det(J) for the load f = 1."""
+    return np.linalg.det(shell_jacobian(e1, e2, e3))
 
 
 # ---------------------------------------------------------------------------

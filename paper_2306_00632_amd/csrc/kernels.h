@@ -67,8 +67,12 @@ void column_energy(hipStream_t s, const double* P, int rows, int a, double* part
 // the S partials of column j): sort energies descending, keep the smallest
 // s whose discarded tail is <= budget, where budget = eps^2 * norm2 / 3 and
 // norm2 = *norm2_io (if set_norm, norm2 is first set to sum(e)).  Writes
-// sel[0] = s, sel[1..s] = order; tail energy to disc[0] and s (as a double)
-// to disc[1].
+// sel[0] = s, sel[1..a] = the columns in descending energy order; tail energy
+// to disc[0], s (as a double) to disc[1], k1 to disc[2] and sum(e) to
+// disc[3], where k1 counts the columns whose energy e is at least
+// max(64 a eps_mach sum(e), 10 (a eps_mach e_max)^2 / budget): directions a
+// Gram matrix of this mode resolves, with eigenvectors whose rounding leaks
+// less than a tenth of the budget into the other directions.
 void select_rank(hipStream_t s, const double* part, int S, int a, double eps, double* norm2_io,
                  int set_norm, int* sel, double* disc);
 

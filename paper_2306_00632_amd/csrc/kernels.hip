@@ -137,6 +137,7 @@ void column_energy(hipStream_t s, const double* P, int rows, int a, double* part
 }
 
 constexpr int kSelMax = 2048;
+constexpr double kGramNoise = 64.0;
 
 __global__ __launch_bounds__(1024) void k_select(const double* __restrict__ part, int S, int a, double eps,
                                                  double* norm2_io, int set_norm, int* sel,
@@ -188,13 +189,23 @@ __global__ __launch_bounds__(1024) void k_select(const double* __restrict__ part
       if (tail + v <= budget) { tail += v; s = i; }
       else break;
     }
+    // directions resolved by the Gram matrix: rounding in G = A A^T (about
+    // a eps_mach ||A||^2) mixes the eigenvectors of smaller energies, and an
+    // eigenvector of energy e leaks about (a eps_mach e_max)^2 / e of energy
+    // into the others, which must stay a tenth of the budget
+    const double ua = a * 2.220446049250313e-16;
+    const double thr = budget > 0.0 ? fmax(kGramNoise * ua * tot, 10.0 * (ua * key[0]) * (ua * key[0]) / budget)
+                                    : 2.0 * key[0] + 1.0;
+    int k1 = 0;
+    while (k1 < a && key[k1] >= thr) ++k1;
     sel[0] = s;
     disc[0] = tail;
     disc[1] = (double)s;  // the rank again, beside the tail, for a single readback
+    disc[2] = (double)k1;
+    disc[3] = tot;
   }
   __syncthreads();
-  const int s = sel[0];
-  for (int i = threadIdx.x; i < s; i += 1024) sel[1 + i] = idx[i];
+  for (int i = threadIdx.x; i < a; i += 1024) sel[1 + i] = idx[i];
 }
 
 void select_rank(hipStream_t s, const double* part, int S, int a, double eps, double* norm2_io,

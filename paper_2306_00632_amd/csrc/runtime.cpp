@@ -128,6 +128,7 @@ struct tk_ctx {
   std::vector<hipEvent_t> evpool;
   double p_ms[tk::PK_N] = {}, p_bytes[tk::PK_N] = {}, p_flops[tk::PK_N] = {};
   long long p_n[tk::PK_N] = {};
+  long long tail_refinements = 0;  // ST-HOSVD modes whose tail needed a second eigendecomposition
 };
 
 namespace tk {
@@ -565,7 +566,52 @@ static void spec_join(tk_ctx* ctx, const TruncPrep& P, int i) {
   if (P.Vs[i]) HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_side[i], 0));
 }
 
-static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double* disc_rel) {
+// Second level of one ST-HOSVD mode's eigendecomposition.  The Gram matrix
+// G = A A^T of the mode unfolding A (a x bc) carries rounding errors of about
+// a eps_mach ||A||^2, so its eigenvectors are reliable only for energies
+// well above that (the k1 leading columns of V in the order sel[1..a]); the
+// other a - k1 eigenvectors V_r are orthonormal and orthogonal to them but
+// mix the small singular directions among themselves.  Their coordinates
+// M = V_r^T A are the columns P_r of Pm = A^T V already at hand, whose Gram
+// H = P_r^T P_r ((a - k1) x (a - k1)) resolves the tail relative to its own
+// norm; with H = Y diag(mu) Y^T the refined basis is [V_k1, V_r Y] and the
+// mode coordinates [P_k1, P_r Y].  V (a x a) and Pm (bc x a) are replaced.
+// Returns how many leading refined directions are themselves resolved (the
+// same test as the rank selection's, on the eigenvalues mu of H).
+static int refine_tail(tk_ctx* ctx, int a, int bc, int k1, const int* sel, double budget, BufP& V, BufP& Pm) {
+  const int m = a - k1;
+  const int* order = sel + 1;  // device: columns in descending energy order
+  BufP Vn = alloc(ctx, (size_t)a * a), Pn = alloc(ctx, (size_t)bc * a);
+  BufP Vr = alloc(ctx, (size_t)a * m), Pr = alloc(ctx, (size_t)bc * m);
+  {
+    Prof pr(ctx, PK_SELECT, 16.0 * ((double)a * a + (double)bc * a), 0.0);
+    gpu::gather_columns(ctx->stream, V->p, a, order, k1, Vn->p);
+    gpu::gather_columns(ctx->stream, Pm->p, bc, order, k1, Pn->p);
+    gpu::gather_columns(ctx->stream, V->p, a, order + k1, m, Vr->p);
+    gpu::gather_columns(ctx->stream, Pm->p, bc, order + k1, m, Pr->p);
+  }
+  BufP H = alloc(ctx, (size_t)m * m), Y = alloc(ctx, (size_t)m * m), mu = alloc(ctx, (size_t)m);
+  gemm(ctx, true, false, m, m, bc, 1.0, Pr->p, bc, Pr->p, bc, 0.0, H->p, m);
+  {
+    BufP work = alloc(ctx, gpu::sym_eig_work(m));
+    Prof pr(ctx, PK_EIG, 8.0 * 2.0 * m * (double)m, eig_flops(m));
+    gpu::sym_eig(ctx->stream, H->p, m, Y->p, mu->p, work->p);
+  }
+  gemm(ctx, false, false, a, m, m, 1.0, Vr->p, a, Y->p, m, 0.0, Vn->p + (size_t)a * k1, a);
+  gemm(ctx, false, false, bc, m, m, 1.0, Pr->p, bc, Y->p, m, 0.0, Pn->p + (size_t)bc * k1, bc);
+  V = Vn;
+  Pm = Pn;
+  const auto hmu = d2h(ctx, mu->p, (size_t)m);  // descending
+  double sum = 0.0;
+  for (double v : hmu) sum += std::max(v, 0.0);
+  const double um = m * 2.220446049250313e-16, top = std::max(hmu[0], 0.0);
+  const double thr = budget > 0.0 ? std::max(64.0 * um * sum, 10.0 * (um * top) * (um * top) / budget) : 2.0 * top + 1.0;
+  int k_add = 0;
+  while (k_add < m && hmu[k_add] >= thr) ++k_add;
+  return k_add;
+}
+
+static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double* disc_rel, bool refine = true) {
   int dims[3] = {P.q[0], P.q[1], P.q[2]};
   BufP cur = P.Z;
   BufP S[3];
@@ -626,8 +672,25 @@ static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double*
       Prof pr(ctx, PK_SELECT, 8.0 * a * (double)nseg, 0.0);
       gpu::select_rank(ctx->stream, part->p, nseg, a, eps, norm2, k == 0 ? 1 : 0, sel, disc);
     }
-    // one readback of [norm2, tail, s] (scal + 300 .. 302)
-    const auto hv = d2h(ctx, norm2, 3);
+    // one readback of [norm2, tail, s, k1, mode energy] (scal + 300 .. 304)
+    auto hv = d2h(ctx, norm2, 5);
+    // kept directions that the Gram matrix does not resolve have energies
+    // smeared by rounding, which can keep up to all a of them: refine the
+    // unresolved tail (up to three levels) while the cut lies inside it
+    int k_res = (int)hv[3];
+    for (int level = 0; refine && level < 3 && (int)hv[2] > k_res && k_res >= 1 && k_res < a; ++level) {
+      const double budget = eps * eps * hv[0] / 3.0;
+      const int k_add = refine_tail(ctx, a, bc, k_res, sel, budget, V, Pm);
+      part = alloc(ctx, (size_t)a * nseg);
+      {
+        Prof pr(ctx, PK_SELECT, 8.0 * bc * (double)a + 8.0 * a * (double)nseg, 2.0 * bc * (double)a);
+        gpu::column_energy(ctx->stream, Pm->p, bc, a, part->p);
+        gpu::select_rank(ctx->stream, part->p, nseg, a, eps, norm2, 0, sel, disc);
+      }
+      hv = d2h(ctx, norm2, 5);
+      k_res += std::max(k_add, 1);
+      ++ctx->tail_refinements;
+    }
     if (k == 0) P.norm2 = hv[0];
     const double hdisc = hv[1];
     const int hsel = (int)hv[2];
@@ -677,9 +740,9 @@ static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double*
   return t;
 }
 
-static tk_tucker* truncate(tk_ctx* ctx, const tk_tucker* y, double eps, double* disc) {
+static tk_tucker* truncate(tk_ctx* ctx, const tk_tucker* y, double eps, double* disc, bool refine = true) {
   TruncPrep P = truncate_prepare(ctx, y);
-  return truncate_finish(ctx, P, eps, disc);
+  return truncate_finish(ctx, P, eps, disc, refine);
 }
 
 static double core_norm(tk_ctx* ctx, const tk_tucker* t) {
@@ -847,7 +910,7 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
   Owned r(scaled_copy(ctx, f.t, 1.0));  // r_0 = f (x_0 = 0)
   double nr = 1.0;
   if (r.t->blocks.size() != 1) {
-    r = Owned(truncate(ctx, r.t, 0.0, nullptr));
+    r = Owned(truncate(ctx, r.t, 0.0, nullptr, 0.0 < prm.refine_below));
     nr = core_norm(ctx, r.t);
   }
   double eta = beta * tol / nr;
@@ -857,11 +920,11 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
     return on;
   };
   Owned pz(apply_prec(ctx, P, r.t, f32()));
-  Owned z(truncate(ctx, pz.t, eta, nullptr));
+  Owned z(truncate(ctx, pz.t, eta, nullptr, eta < prm.refine_below));
   pz = Owned();
   Owned p(scaled_copy(ctx, z.t, 1.0));
   Owned ap(apply_op(ctx, op, p.t, f32()));
-  Owned q(truncate(ctx, ap.t, eta, nullptr));
+  Owned q(truncate(ctx, ap.t, eta, nullptr, eta < prm.refine_below));
   ap = Owned();
   inf.trel_calls = 2;
   double xi = dot(ctx, p.t, q.t);
@@ -880,7 +943,7 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
     double eps_new = eps;
     Owned x1;
     while (true) {
-      x1 = Owned(truncate_finish(ctx, prep, eps_new, nullptr));
+      x1 = Owned(truncate_finish(ctx, prep, eps_new, nullptr, eps_new < prm.refine_below));
       ++inf.trel_calls;
       if (den == 0.0) break;
       const double v = (om * dot(ctx, p.t, x1.t) - base) / den;
@@ -895,7 +958,7 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
     Owned ax(apply_op(ctx, op, x.t));
     Owned res(lin_comb(ctx, 1.0, f.t, -1.0, ax.t));
     ax = Owned();
-    r = Owned(truncate(ctx, res.t, eta, nullptr));
+    r = Owned(truncate(ctx, res.t, eta, nullptr, eta < prm.refine_below));
     res = Owned();
     ++inf.trel_calls;
     nr = core_norm(ctx, r.t);
@@ -907,14 +970,14 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
     if (nr <= tol) break;
     eta = beta * tol / nr;
     pz = Owned(apply_prec(ctx, P, r.t, f32()));
-    z = Owned(truncate(ctx, pz.t, eta, nullptr));
+    z = Owned(truncate(ctx, pz.t, eta, nullptr, eta < prm.refine_below));
     pz = Owned();
     const double bk = -dot(ctx, z.t, q.t) / xi;
     Owned zp(lin_comb(ctx, 1.0, z.t, bk, p.t));
-    p = Owned(truncate(ctx, zp.t, eta, nullptr));
+    p = Owned(truncate(ctx, zp.t, eta, nullptr, eta < prm.refine_below));
     zp = Owned();
     ap = Owned(apply_op(ctx, op, p.t, f32()));
-    q = Owned(truncate(ctx, ap.t, eta, nullptr));
+    q = Owned(truncate(ctx, ap.t, eta, nullptr, eta < prm.refine_below));
     ap = Owned();
     xi = dot(ctx, p.t, q.t);
     inf.trel_calls += 3;
@@ -971,7 +1034,7 @@ static tk_status tpcg_block(tk_ctx* ctx, const tk_op* const A[9], const tk_prec*
     for (int a = 0; a < 3; ++a) out[a] = v[a].t;
   };
   auto trunc = [&](Owned* y, double eps, Owned* out) {
-    for (int a = 0; a < 3; ++a) out[a] = Owned(truncate(ctx, y[a].t, eps, nullptr));
+    for (int a = 0; a < 3; ++a) out[a] = Owned(truncate(ctx, y[a].t, eps, nullptr, eps < prm.refine_below));
     inf.trel_calls += 1;
   };
   // ||r|| of a truncated block vector (orthonormal factors per component)
@@ -1044,7 +1107,7 @@ static tk_status tpcg_block(tk_ctx* ctx, const tk_op* const A[9], const tk_prec*
     double eps_new = eps;
     Owned x1[3];
     while (true) {
-      for (int a = 0; a < 3; ++a) x1[a] = Owned(truncate_finish(ctx, prep[a], eps_new, nullptr));
+      for (int a = 0; a < 3; ++a) x1[a] = Owned(truncate_finish(ctx, prep[a], eps_new, nullptr, eps_new < prm.refine_below));
       ++inf.trel_calls;
       if (den == 0.0) break;
       const double v = (om * bdot(p, x1) - base) / den;
@@ -1784,6 +1847,12 @@ tk_status tk_prof_enable(tk_ctx* ctx, int32_t on) {
   });
 }
 
+tk_status tk_truncate_refinements(const tk_ctx* ctx, int64_t* count) {
+  if (!ctx || !count) return TK_EINVAL;
+  *count = ctx->tail_refinements;
+  return TK_OK;
+}
+
 tk_status tk_prof_reset(tk_ctx* ctx) {
   if (!ctx) return TK_EINVAL;
   return guarded(ctx, [&]() {
@@ -1892,6 +1961,7 @@ void tk_tpcg_defaults(tk_tpcg_params* p) {
   p->maxit = 1000;
   p->verbose = 0;
   p->arith = TK_ARITH_F64;
+  p->refine_below = 1e-8;
 }
 
 tk_status tpcg_solve(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_tucker* f,

@@ -36,7 +36,8 @@ class CoreNz(C.Structure):
 class TpcgParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("beta", C.c_double), ("eps0", C.c_double),
                 ("alpha", C.c_double), ("eps_min", C.c_double), ("delta", C.c_double),
-                ("maxit", C.c_int32), ("verbose", C.c_int32), ("arith", C.c_int32)]
+                ("maxit", C.c_int32), ("verbose", C.c_int32), ("arith", C.c_int32),
+                ("refine_below", C.c_double)]
 
 
 class TpcgInfo(C.Structure):
@@ -55,6 +56,7 @@ EXPORTS = {
     "tk_assemble_1d_bc": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, C.c_int32, dp]),
     "tk_assemble_1d_cheb": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, C.c_int32, dp]),
     "tk_load_vector_1d_cheb": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, C.c_int32, dp]),
+    "tk_truncate_refinements": (C.c_int32, [vp, i64p]),
     "tk_basis_values_1d": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64, dp, dp]),
     "tk_load_vector_1d": (C.c_int32, [C.c_int32, C.c_int32, dp, dp]),
     "tk_fd_direction_host": (C.c_int32, [C.c_int32, C.c_int32, C.c_double, i32p, i32p, i32p, dp, dp, dp, dp]),
@@ -263,6 +265,12 @@ class Context:
 
     def sync(self):
         self.check(lib().tk_ctx_sync(self.h), "sync")
+
+    def truncate_refinements(self) -> int:
+        """ST-HOSVD modes refined by a second eigendecomposition of their tail."""
+        c = C.c_int64()
+        self.check(lib().tk_truncate_refinements(self.h, C.byref(c)), "tk_truncate_refinements")
+        return c.value
 
     PROF_KINDS = ["band_apply", "dgemm", "householder_qr", "sym_eig", "select_rank",
                   "fd_forward", "fd_backward", "misc"]

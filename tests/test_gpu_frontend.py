@@ -138,3 +138,63 @@ def test_tpcg_annulus_iterations_are_robust(ctx, p):
     say(f"annulus p={p} iterations {its}")
     assert its[("scaled", 128)] <= 12 and abs(its[("scaled", 128)] - its[("scaled", 64)]) <= 1
     assert its[("parametric", 128)] < 26
+
+
+def test_shell_operator_and_solve(ctx):
+    """The spherical-shell stand-in (gnomonic patch, not a tensor product,
+    Q_23 != 0; load f = 1): the ranks of the separable Q entries and of omega
+    against the oracle's, the operator applied to a random Tucker tensor
+    against the oracle's (1e-7: both truncate at eps = 1e-10 of the largest
+    sampled value, ranks are not exact here), and TPCG against the oracle's
+    sparse direct solve of the oracle's system (1e-6)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    from paper_2306_00632_amd import geometry, tk
+    n_el, p, t, eps = 8, 2, 33, 1e-10
+    say("front end shell operator and solve")
+    q, omega = W.shell_samples(t)
+    op, ranks = geometry.operator(ctx, n_el, p, q, eps)
+    op_o, ranks_o = fe.operator(n_el, p, fe.shell_jacobian, t, eps)
+    assert {kl: tuple(r) for kl, r in ranks.items()} == ranks_o
+    n = n_el + p - 2
+    core, U = W.random_tucker((n, n, n), (3, 2, 4), 9)
+    y = to_oracle(tk.tucker_apply_op(ctx, op, tk.Tucker.from_host(ctx, core, U))).full()
+    err = rel(y, T.apply_op(op_o, T.Tucker(core, U)).full())
+    say(f"   ranks={ranks} apply rel={err:.2e}")
+    assert err <= 1e-7
+    f = geometry.rhs(ctx, n_el, p, omega, eps)
+    f_o = fe.rhs(n_el, p, fe.shell_omega, t, eps)
+    A = sum(c * sp.kron(sp.csr_matrix(op_o.mats[2][i3]), sp.kron(sp.csr_matrix(op_o.mats[1][i2]),
+                                                                  sp.csr_matrix(op_o.mats[0][i1])))
+            for i1, i2, i3, c in op_o.nnz)
+    xd = spla.spsolve(A.tocsc(), f_o.full().reshape(-1, order="F")).reshape((n, n, n), order="F")
+    x, info = tk.tpcg_solve(ctx, op, tk.Preconditioner.create(ctx, n_el, p, 0.1, geometry.fd_coefficients(q)), f,
+                            tol=1e-10)
+    err = rel(to_oracle_plain(x).full(), xd)
+    say(f"   iters={info['iters']} rank={info['rank']} rel_vs_direct={err:.2e}")
+    assert info["converged"] and err <= 1e-6
+
+
+def test_tight_tolerance_ranks_with_tail_refinement(ctx):
+    """TPCG at tol = 1e-10 on the annulus (n_el = 64, p = 3; front-end
+    eps = 1e-11): with the truncations below 1e-8 refined (the default
+    refine_below) the solution's ranks are smaller than with the Gram
+    eigenvectors alone (refine_below = 0), where noise-level directions are
+    kept, and the two solutions agree to the solver tolerance."""
+    from paper_2306_00632_amd import geometry, tk
+    n_el, p = 64, 3
+    q, _, _ = W.annulus_samples(33)
+    _, omega, _ = W.annulus_samples(64)
+    op, _ = geometry.operator(ctx, n_el, p, q, 1e-11)
+    f = geometry.rhs(ctx, n_el, p, omega, 1e-11)
+    P = tk.Preconditioner.create(ctx, n_el, p, 0.1, geometry.fd_coefficients(q))
+    before = ctx.truncate_refinements()
+    x1, i1 = tk.tpcg_solve(ctx, op, P, f, tol=1e-10)
+    refined = ctx.truncate_refinements() - before
+    x0, i0 = tk.tpcg_solve(ctx, op, P, f, tol=1e-10, refine_below=0.0)
+    say(f"   refined: iters={i1['iters']} rank={i1['rank']} ({refined} refinements); "
+        f"Gram only: iters={i0['iters']} rank={i0['rank']}")
+    assert i1["converged"] and i0["converged"] and refined > 0
+    assert max(i1["rank"]) < max(i0["rank"])
+    X1, X0 = to_oracle_plain(x1).full(), to_oracle_plain(x0).full()
+    assert rel(X1, X0) <= 1e-8

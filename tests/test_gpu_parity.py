@@ -155,6 +155,37 @@ def test_truncate_rank_deficient_and_zero(ctx):
     assert te.shape()[1] == (0, 0, 0)
 
 
+@pytest.mark.parametrize("eps", [1e-6, 1e-9, 1e-11])
+def test_truncate_ranks_below_the_gram_noise(ctx, eps):
+    """A planted multilinear spectrum sigma_i = 10^{-i/2}, i < 29 (a
+    superdiagonal core rotated by random orthogonal matrices in every mode,
+    so that no unfolding is diagonal, and random orthonormal factors of 60
+    rows): the exact ST-HOSVD ranks are 13, 19 and 23 at eps = 1e-6, 1e-9
+    and 1e-11 (each a factor 3 away from the next tail energy), and the
+    library's Algorithm 1 matches the oracle's SVD-based ranks and the error
+    bound of eq. rel_estimate although below eps = 1e-8 the cut lies among
+    energies under 64 a eps_mach of the total, which a Gram matrix does not
+    resolve (the two-level eigendecomposition of the tail is counted)."""
+    tk, _ = lib_modules()
+    say(f"truncate below the Gram noise eps={eps:g}")
+    rng = np.random.default_rng(77)
+    r, n = 29, 60
+    G = np.zeros((r, r, r))
+    for i in range(r):
+        G[i, i, i] = 10.0 ** (-i / 2.0)
+    for k in range(3):
+        G = T.mode_product(G, np.linalg.qr(rng.standard_normal((r, r)))[0], k)
+    U = [np.linalg.qr(rng.standard_normal((n, r)))[0] for _ in range(3)]
+    yo = T.Tucker(G, U)
+    yg = tk.Tucker.from_host(ctx, G, U)
+    before = ctx.truncate_refinements()
+    _check_trunc(ctx, T.as_sum(yo), yg, eps)
+    expected = {1e-6: 13, 1e-9: 19, 1e-11: 23}[eps]
+    assert T.trel(T.as_sum(yo), eps).ranks == (expected,) * 3
+    if eps < 1e-7:
+        assert ctx.truncate_refinements() > before
+
+
 # --- preconditioner (Algorithm 4) --------------------------------------------------------
 
 @pytest.mark.parametrize("n_el,p", [(16, 2), (16, 3), (32, 4), (128, 3), (64, 5)])

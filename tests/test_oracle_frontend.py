@@ -83,7 +83,7 @@ def test_load_is_minus_laplacian_of_the_solution():
     assert np.abs(f + lap).max() <= 1e-5 * np.abs(f).max()
 
 
-def _brute_force_stiffness(n_el, p, nq=8):
+def _brute_force_stiffness(n_el, p, nq=8, jacobian=fe.annulus_jacobian):
     """int grad B_i^T Q grad B_j over [0,1]^3 with the exact Q, tensor Gauss."""
     kn = bspline.open_knots(n_el, p)
     x, w = bspline.gauss_points(n_el, nq)
@@ -91,7 +91,7 @@ def _brute_force_stiffness(n_el, p, nq=8):
     n = B[0].shape[1]
     E1, E2, E3 = np.meshgrid(x, x, x, indexing="ij")
     W = w[:, None, None] * w[None, :, None] * w[None, None, :]
-    J = fe.annulus_jacobian(E1, E2, E3)
+    J = jacobian(E1, E2, E3)
     Ji = np.linalg.inv(J)
     Q = np.linalg.det(J)[..., None, None] * np.einsum("...ka,...la->...kl", Ji, Ji)
     A = np.zeros((n ** 3, n ** 3))
@@ -173,3 +173,41 @@ def test_front_end_chebyshev_transform_matches_the_vandermonde_inverse():
         V = chebyshev.chebvander(2.0 * fe.cheb_points(t) - 1.0, t - 1)
         np.testing.assert_allclose(geometry.cheb_transform(t), np.linalg.inv(V), atol=1e-12)
     np.testing.assert_allclose(geometry.cheb_points(7), fe.cheb_points(7), atol=0)
+
+
+def test_shell_jacobian_matches_finite_differences():
+    """The shell's analytic Jacobian against central differences of its map,
+    and its image on the spheres of radii 1 and 2."""
+    P = np.random.default_rng(5).uniform(0.05, 0.95, (12, 3))
+    J = fe.shell_jacobian(*P.T)
+    h = 1e-6
+    for b in range(3):
+        e = np.zeros(3)
+        e[b] = h
+        fd = (np.stack(fe.shell_map(*(P + e).T), -1) - np.stack(fe.shell_map(*(P - e).T), -1)) / (2 * h)
+        assert np.abs(J[:, :, b] - fd).max() <= 1e-8, b
+    for r0, e1 in ((1.0, 0.0), (2.0, 1.0)):
+        X = np.stack(fe.shell_map(np.full(12, e1), P[:, 1], P[:, 2]), -1)
+        np.testing.assert_allclose(np.linalg.norm(X, axis=1), r0, atol=1e-14)
+
+
+def test_shell_operator_and_samples():
+    """The shell's Tucker matrix equals brute-force quadrature of
+    grad B_i^T Q grad B_j (a geometry that is not a tensor product and not
+    orthogonal: Q_23 != 0 gets a nonzero rank, Q_1a none), and the seeded
+    closed-form samples of Q and omega match the oracle's from the Jacobian."""
+    import workloads
+    op, ranks = fe.operator(3, 2, fe.shell_jacobian, 33, 1e-12)
+    assert ranks[(0, 1)] == ranks[(1, 0)] == ranks[(0, 2)] == (0, 0, 0)
+    assert ranks[(1, 2)][0] == 1 and min(ranks[(1, 2)][1:]) >= 2
+    A = op.dense()
+    Ab = _brute_force_stiffness(3, 2, nq=10, jacobian=fe.shell_jacobian)
+    assert np.abs(A - Ab).max() <= 1e-9 * np.abs(Ab).max()
+    t = 9
+    q, omega = workloads.shell_samples(t)
+    for k in range(3):
+        for l in range(3):
+            ref = fe.grid_values(fe.q_entry(fe.shell_jacobian, k, l), t)
+            assert np.abs(q[(k, l)] - ref).max() <= 1e-13 * 4.0, (k, l)
+    ref = fe.grid_values(fe.shell_omega, t)
+    assert np.abs(omega - ref).max() <= 1e-13 * np.abs(ref).max()

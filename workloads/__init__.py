@@ -267,3 +267,22 @@ def annulus_samples(t: int) -> tuple:
         rho2 = X * X + Y * Y
         return (rho2 - 1.0) * (rho2 - 4.0) * np.sin(np.pi * Z) * np.sin(7.0 * X * Y)
     return q, omega, u
+
+
+def shell_samples(t: int) -> tuple:
+    """Samples on the same grid for a piece of a spherical shell (radii 1 and
+    2) over a gnomonic patch, F(eta) = rho w / |w|, rho = 1 + eta_1,
+    w = (1, u, v), u = eta_2, v = eta_3: with D = 1 + u^2 + v^2 the metric
+    of the patch gives det(J) = rho^2 D^{-3/2}, Q_11 = rho^2 D^{-3/2},
+    Q_22 = (1 + u^2) D^{-1/2}, Q_33 = (1 + v^2) D^{-1/2},
+    Q_23 = Q_32 = u v D^{-1/2} and Q_1a = 0; omega = det(J) (load f = 1).
+    Returns (q, omega)."""
+    x = 0.5 * (1.0 + np.cos(np.pi * np.arange(t) / (t - 1)))
+    R, U, V = np.meshgrid(1.0 + x, x, x, indexing="ij")
+    D = 1.0 + U * U + V * V
+    q = {(k, l): np.zeros((t, t, t)) for k in range(3) for l in range(3)}
+    q[(0, 0)] = R * R * D ** -1.5
+    q[(1, 1)] = (1.0 + U * U) / np.sqrt(D)
+    q[(2, 2)] = (1.0 + V * V) / np.sqrt(D)
+    q[(1, 2)] = q[(2, 1)] = U * V / np.sqrt(D)
+    return q, R * R * D ** -1.5
