@@ -269,7 +269,7 @@ def boundary_conditions(ctx, reps=3):
 
 
 def mapped_domain(ctx, domain="annulus", p_list=(2, 3, 4, 5), n_el_list=(128, 256, 512, 1024), scaled_p=(3,),
-                  manufactured=True):
+                  manufactured=True, maxit=400):
     """Sec. 5.1-5.2's mapped domains through the Appendix A front end: the
     thick quarter annulus with the manufactured solution, or the stand-in
     spherical shell (a gnomonic patch, radii 1 and 2) with f = 1.  Q and
@@ -278,11 +278,13 @@ def mapped_domain(ctx, domain="annulus", p_list=(2, 3, 4, 5), n_el_list=(128, 25
     paper's eps = max(tol / 10, 1e-12), the 1D matrices and moments of the
     factor columns assembled on the host, and TPCG run at tol = 1e-6 with
     eps_prec = 0.1.  Per (p, n_el): the iterations (the paper's tables
-    report 12 everywhere for the annulus and 74-106 for its shell), the
+    report 12 everywhere for the annulus and 74-106 for its shell; the
+    default run takes the shell to n_el = 256, where a solve takes seconds), the
     solution rank, the front-end, FD-setup and solve times, with the FD of
     the parametric Laplacian (eq. FD_prec with unit coefficients) and, for p
     in scaled_p, with the mean of each diagonal entry of Q as direction
-    coefficient.  For the annulus with manufactured=True, a solve at
+    coefficient; a run that reaches maxit iterations is reported with
+    converged = false.  For the annulus with manufactured=True, a solve at
     n_el = 128, p = 3, tol = 1e-10 gives the error to the manufactured
     solution on a 9^3 grid of parametric points (max-norm, relative)."""
     import numpy as np
@@ -318,10 +320,11 @@ def mapped_domain(ctx, domain="annulus", p_list=(2, 3, 4, 5), n_el_list=(128, 25
                 P = tk.Preconditioner.create(ctx, n_el, p, 0.1, c)
                 ctx.sync()
                 t3 = time.perf_counter()
-                x, info = tk.tpcg_solve(ctx, op, P, f, tol=tol)
+                x, info = tk.tpcg_solve(ctx, op, P, f, allow_noconv=True, tol=tol, maxit=maxit)
                 ctx.sync()
                 t4 = time.perf_counter()
                 out["runs"].append({"p": p, "n_el": n_el, "fd": fd, "iters": info["iters"],
+                                    "converged": info["converged"],
                                     "relres": info["relres"], "rank": list(info["rank"]),
                                     "rhs_rank": list(f.shape()[1]), "front_end_ms": 1e3 * (t1 - t0),
                                     "fd_setup_ms": 1e3 * (t3 - t2), "solve_ms": 1e3 * (t4 - t3)})
@@ -576,18 +579,25 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    def section(name, fn, *a):
+        t0 = time.perf_counter()
+        out[name] = fn(*a)
+        print(f"bench: {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    print(f"bench: {args.steps} timed solves done, {1e3 * total / max(args.steps, 1):.1f} ms each",
+          file=sys.stderr, flush=True)
     if not args.no_hbm:
-        out["mode_products_hbm"] = mode_products_hbm(ctx)
-        out["matrix_cores"] = matrix_cores(ctx, kernels)
+        section("mode_products_hbm", mode_products_hbm, ctx)
+        section("matrix_cores", matrix_cores, ctx, kernels)
     if not args.no_bc:
-        out["boundary_conditions"] = boundary_conditions(ctx)
+        section("boundary_conditions", boundary_conditions, ctx)
     if not args.no_annulus:
-        out["annulus"] = mapped_domain(ctx, "annulus")
-        out["shell"] = mapped_domain(ctx, "shell")
+        section("annulus", mapped_domain, ctx, "annulus")
+        section("shell", lambda: mapped_domain(ctx, "shell", n_el_list=(128, 256)))
     if not args.no_serve:
-        out["serving"] = serving(args.serve_slots)
+        section("serving", serving, args.serve_slots)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
-        out["cpu_baseline"] = cpu_baseline(w, last_info["iters"], exact=(args.fd == "exact"))
+        section("cpu_baseline", lambda: cpu_baseline(w, last_info["iters"], exact=(args.fd == "exact")))
     print(json.dumps(out), flush=True)
 
 

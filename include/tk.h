@@ -324,7 +324,8 @@ typedef struct {
   double beta;     /* eta_k = beta tol ||f|| / ||r_k||, eq. rel_tol_iterates (0.1) */
   double eps0;     /* initial dynamic-truncation tolerance (0.1) */
   double alpha;    /* reduction factor of Algorithm 2 (0.5) */
-  double eps_min;  /* floor of Algorithm 2; <= 0 means 0.1 * tol (Sec. 5) */
+  double eps_min;  /* floor of Algorithm 2; <= 0 means tol ||f|| / 10 with the
+                      given rhs' norm (Sec. 5), at most tol / 10 */
   double delta;    /* update-ratio threshold of Algorithm 2 (1e-3) */
   int32_t maxit;   /* iteration cap (1000) */
   int32_t verbose; /* 1: print one line per iteration to stderr */

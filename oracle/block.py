@@ -106,7 +106,8 @@ def btdt(y_k: list, y_tilde: list, dy_tilde: list, eps: float, alpha: float, eps
 def tpcg(A: dict, prec: BlockFD, f: list, tol=1e-6, beta=0.1, eps0=0.1, alpha=0.5, eps_min=None,
          delta=1e-3, maxit=1000):
     """Algorithm 5 on block vectors, with the readings of oracle.tpcg (rhs
-    normalised to norm 1 and the solution scaled back, x_0 = 0, eta_k as
+    normalised to norm 1 and the solution scaled back, eps_min = tol / 10
+    times min(1, ||f||), x_0 = 0, eta_k as
     printed, early exit when ||r_{k+1}|| <= tol, breakdown on xi <= 0)."""
     nf = bnorm(f)
     n = f[0].n
@@ -114,7 +115,7 @@ def tpcg(A: dict, prec: BlockFD, f: list, tol=1e-6, beta=0.1, eps0=0.1, alpha=0.
         return [Tucker.zero(n) for _ in range(3)], TPCGInfo(converged=True)
     f = [Tucker(f[a].core / nf, f[a].U) for a in range(3)]
     if eps_min is None:
-        eps_min = 0.1 * tol
+        eps_min = 0.1 * tol * min(1.0, nf)
     info = TPCGInfo()
     x = [Tucker.zero(n) for _ in range(3)]
     r = f

@@ -13,7 +13,10 @@ Readings (listed in DESIGN.md):
   truncated by ST-HOSVD so that the discarded coefficients have Frobenius
   norm at most eps times the largest value on the grid (for Q, the largest
   over its entries, so that entries that vanish up to rounding are dropped,
-  as the paper's zero ranks for the annulus' off-diagonal entries show); the
+  as the paper's zero ranks for the annulus' off-diagonal entries show), and
+  Q being symmetric, the entries below the diagonal reuse the approximation
+  of their mirror, so that the Tucker matrix is exactly symmetric (separate
+  approximations differ at the eps level and make CG stagnate); the
   paper's acceptance test (error <= 10 eps at Halton points) is read relative
   to that scale and checked;
 * Chebyshev polynomials are those of [0, 1]: T_m(2 eta - 1);
@@ -201,9 +204,12 @@ def operator(n_el: int, p: int, jac, t: int, eps: float):
     nnz = []
     ranks = {}
     scale = max(float(np.abs(grid_values(q_entry(jac, k, l), t)).max()) for k in range(3) for l in range(3))
+    seps = {}
     for k in range(3):
         for l in range(3):
-            g = separable(q_entry(jac, k, l), t, eps, scale)
+            # Q = Q^T: below the diagonal, the mirror entry's approximation
+            g = seps[(l, k)] if k > l else separable(q_entry(jac, k, l), t, eps, scale)
+            seps[(k, l)] = g
             ranks[(k, l)] = tuple(g.core.shape)
             if g.core.size == 0:
                 continue

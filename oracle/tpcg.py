@@ -6,8 +6,11 @@ Algorithm 4.
 
 Readings (listed in DESIGN.md):
 * the rhs is normalised to ||f|| = 1 internally and the solution scaled back,
-  so the absolute test ||r_k|| > tol of Algorithm 5, the "relative tolerance"
-  of Sec. 5 and eps_min = tol ||f|| / 10 all agree;
+  so the absolute test ||r_k|| > tol of Algorithm 5 and the "relative
+  tolerance" of Sec. 5 agree; eps_min = tol ||f~|| / 10 (Sec. 5) is taken
+  with the norm of the given rhs (for IgA load vectors ||f~|| ~ n_el^{-3/2},
+  so the floor tightens under refinement), capped at tol / 10 when
+  ||f~|| > 1;
 * eta_k follows eq. (rel_tol_iterates) as printed;
 * x_0 = 0 (Sec. 5), so r_0 = f;
 * when ||r_{k+1}|| <= tol the loop ends before z, p, q are formed (x is not
@@ -42,7 +45,7 @@ def tpcg(op, prec, f: Tucker, tol=1e-6, beta=0.1, eps0=0.1, alpha=0.5,
         return Tucker.zero(n), TPCGInfo(converged=True)
     f = Tucker(f.core / nf, f.U)
     if eps_min is None:
-        eps_min = 0.1 * tol          # tol * ||f~|| * 1e-1 with ||f~|| = 1
+        eps_min = 0.1 * tol * min(1.0, nf)    # tol ||f~|| 1e-1 (Sec. 5), at most tol / 10
     info = TPCGInfo()
     x = Tucker.zero(n)
     r = f                            # r_0 = f - A x_0 with x_0 = 0

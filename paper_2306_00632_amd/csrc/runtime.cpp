@@ -894,9 +894,10 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
                       const tk_tpcg_params& prm, tk_tucker** x_out, tk_tpcg_info* info) {
   tk_tpcg_info inf{};
   const double tol = prm.tol, beta = prm.beta, alpha = prm.alpha, delta = prm.delta;
-  const double eps_min = prm.eps_min > 0 ? prm.eps_min : 0.1 * tol;
   const int n[3] = {f_in->n[0], f_in->n[1], f_in->n[2]};
   const double nf = std::sqrt(std::max(dot(ctx, f_in, f_in), 0.0));
+  // Sec. 5: eps_min = tol ||f~|| / 10 with the given rhs' norm, at most tol / 10
+  const double eps_min = prm.eps_min > 0 ? prm.eps_min : 0.1 * tol * std::min(1.0, nf);
   if (nf == 0.0) {
     int r0[3] = {0, 0, 0};
     *x_out = make_plain(ctx, n, r0);
@@ -1024,7 +1025,6 @@ static tk_status tpcg_block(tk_ctx* ctx, const tk_op* const A[9], const tk_prec*
                             tk_tpcg_info* info) {
   tk_tpcg_info inf{};
   const double tol = prm.tol, beta = prm.beta, alpha = prm.alpha, delta = prm.delta;
-  const double eps_min = prm.eps_min > 0 ? prm.eps_min : 0.1 * tol;
   auto bdot = [&](Owned* x, Owned* y) {
     double s = 0.0;
     for (int a = 0; a < 3; ++a) s += dot(ctx, x[a].t, y[a].t);
@@ -1049,6 +1049,7 @@ static tk_status tpcg_block(tk_ctx* ctx, const tk_op* const A[9], const tk_prec*
   double nf2 = 0.0;
   for (int a = 0; a < 3; ++a) nf2 += dot(ctx, f_in[a], f_in[a]);
   const double nf = std::sqrt(std::max(nf2, 0.0));
+  const double eps_min = prm.eps_min > 0 ? prm.eps_min : 0.1 * tol * std::min(1.0, nf);
   Owned x[3], f[3], r[3], z[3], p[3], q[3], tmp[3];
   int r0[3] = {0, 0, 0};
   for (int a = 0; a < 3; ++a) x[a] = Owned(make_plain(ctx, f_in[a]->n, r0));

@@ -63,7 +63,8 @@ def separable(ctx, values: np.ndarray, eps: float, scale: float | None = None):
 
 def operator(ctx, n_el: int, p: int, q_values, eps: float, bc=((0, 0),) * 3) -> tuple:
     """(Operator, ranks) of eq. matrix_CP from the sampled entries q_values[(k, l)]
-    of Q (t x t x t arrays on the Lobatto grid): per entry with a nonzero
+    of Q (t x t x t arrays on the Lobatto grid; Q symmetric, the entries
+    below the diagonal take their mirror's approximation): per entry with a nonzero
     approximation, its core as a diagonal block and, per mode s and factor
     column, the 1D matrix with the test function differentiated when s = l
     and the trial function when s = k."""
@@ -71,8 +72,13 @@ def operator(ctx, n_el: int, p: int, q_values, eps: float, bc=((0, 0),) * 3) -> 
     bands = [[], [], []]
     nnz = []
     ranks = {}
+    seps = {}
     for (k, l), vals in sorted(q_values.items()):
-        sep = separable(ctx, vals, eps, scale)
+        # Q is symmetric: the entry below the diagonal reuses the approximation
+        # of its mirror, which makes the (l, k) term the transpose of the
+        # (k, l) one and the Tucker matrix exactly symmetric
+        sep = seps[(l, k)] if k > l and (l, k) in seps else separable(ctx, vals, eps, scale)
+        seps[(k, l)] = sep
         if sep is None:
             ranks[(k, l)] = (0, 0, 0)
             continue

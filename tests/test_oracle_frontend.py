@@ -211,3 +211,13 @@ def test_shell_operator_and_samples():
             assert np.abs(q[(k, l)] - ref).max() <= 1e-13 * 4.0, (k, l)
     ref = fe.grid_values(fe.shell_omega, t)
     assert np.abs(omega - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_shell_operator_is_exactly_symmetric():
+    """With the mirrored approximation of Q's lower triangle the Tucker
+    matrix of a non-diagonal Q is symmetric to rounding even at a loose eps
+    (separate approximations of Q_23 and Q_32 would differ at the eps
+    level)."""
+    op, _ = fe.operator(4, 3, fe.shell_jacobian, 17, 1e-4)
+    A = op.dense()
+    assert np.abs(A - A.T).max() <= 1e-13 * np.abs(A).max()
