@@ -178,10 +178,21 @@ __global__ __launch_bounds__(1024) void k_select(const double* __restrict__ part
       __syncthreads();
     }
   }
+  const double norm2 = set_norm ? tot : *norm2_io;
+  const double budget = eps * eps * norm2 / 3.0;
+  // directions resolved by the Gram matrix: rounding in G = A A^T (about
+  // a eps_mach ||A||^2) mixes the eigenvectors of smaller energies, and an
+  // eigenvector of energy e leaks about (a eps_mach e_max)^2 / e of energy
+  // into the others, which must stay a tenth of the budget; the keys are
+  // sorted, so their count is the number of leading resolved columns
+  const double ua = a * 2.220446049250313e-16;
+  const double thr = budget > 0.0 ? fmax(kGramNoise * ua * tot, 10.0 * (ua * key[0]) * (ua * key[0]) / budget)
+                                  : 2.0 * key[0] + 1.0;
+  double cnt = 0.0;
+  for (int i = threadIdx.x; i < a; i += 1024) cnt += key[i] >= thr ? 1.0 : 0.0;
+  const double k1 = block_sum(cnt, red);
   if (threadIdx.x == 0) {
-    double norm2 = set_norm ? tot : *norm2_io;
     if (set_norm) *norm2_io = norm2;
-    const double budget = eps * eps * norm2 / 3.0;
     double tail = 0.0;
     int s = a;
     for (int i = a - 1; i >= 0; --i) {
@@ -189,19 +200,10 @@ __global__ __launch_bounds__(1024) void k_select(const double* __restrict__ part
       if (tail + v <= budget) { tail += v; s = i; }
       else break;
     }
-    // directions resolved by the Gram matrix: rounding in G = A A^T (about
-    // a eps_mach ||A||^2) mixes the eigenvectors of smaller energies, and an
-    // eigenvector of energy e leaks about (a eps_mach e_max)^2 / e of energy
-    // into the others, which must stay a tenth of the budget
-    const double ua = a * 2.220446049250313e-16;
-    const double thr = budget > 0.0 ? fmax(kGramNoise * ua * tot, 10.0 * (ua * key[0]) * (ua * key[0]) / budget)
-                                    : 2.0 * key[0] + 1.0;
-    int k1 = 0;
-    while (k1 < a && key[k1] >= thr) ++k1;
     sel[0] = s;
     disc[0] = tail;
     disc[1] = (double)s;  // the rank again, beside the tail, for a single readback
-    disc[2] = (double)k1;
+    disc[2] = k1;
     disc[3] = tot;
   }
   __syncthreads();
