@@ -1,7 +1,8 @@
 // Symmetric eigendecomposition G = V diag(w) V^T of the Gram matrices of the
 // ST-HOSVD (Sec. 2.3, step 3 of Algorithm 1) on one device.
 //
-// Pipeline (five launches, no host synchronisation):
+// Pipeline (five launches for a <= kTriLdsMax, a few more per column panel
+// beyond; no host synchronisation):
 //   tridiag        Householder reduction Q^T G Q = T (tridiagonal), one
 //                  workgroup; the matrix lives in registers for
 //                  a <= kTriLdsMax, in global memory beyond
@@ -13,7 +14,8 @@
 //   mgs            modified Gram-Schmidt in descending eigenvalue order, a
 //                  second pass when the first met nearly parallel columns
 //                  (clusters of close eigenvalues), so the columns are
-//                  orthonormal to rounding level
+//                  orthonormal to rounding level (beyond kTriLdsMax: block
+//                  Gram-Schmidt, panels projected twice by GEMMs)
 //   backtransform  V = Q X, one wavefront per column
 // The matrix is scaled by a power of two so that max |G_ij| is in [1, 2);
 // w is returned unscaled, in descending order.
@@ -679,114 +681,10 @@ __global__ __launch_bounds__(kInvThreads) void k_invit(int a, const double* __re
             LU + 3 * aa + i, LU + 4 * aa + i, X + i, a);
 }
 
-// Modified Gram-Schmidt over the columns of X in eigenvalue order (columns
-// kept unnormalised during a pass, the squared norms of finished columns in
-// nrm), each pass followed by normalisation; a second pass runs only when
-// the first met a pair of columns with |cos| > 1e-3, as in k_mgs_reg (the
-// running squared norm of every column is tracked in cur).  Xin is
-// [row][column]; Xo receives the orthonormal columns column-major.
-// Global-memory version for a > kTriLdsMax (Xg: a x a scratch): in step j
-// every wavefront updates kMgsCols columns at once, so that their products,
-// reductions and updates overlap the L2 latency of one another.
-constexpr int kMgsCols = 4;
-__global__ __launch_bounds__(kTriThreads) void k_mgs(int a, const double* __restrict__ Xin,
-                                                     double* __restrict__ Xo, double* Xg) {
-  extern __shared__ double ms[];
-  double* Q = Xg;
-  double* nrm = ms;
-  double* cur = ms + a;
-  constexpr int nw = kTriThreads / 64;
-  __shared__ double red[nw];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int aa = a * a;
-  for (int idx = tid; idx < aa; idx += kTriThreads) {
-    const int r = idx % a, c = idx / a;
-    Q[idx] = Xin[(size_t)r * a + c];
-  }
-  __syncthreads();
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int c = wv; c < a; c += nw) {
-      const double* qc = Q + (size_t)c * a;
-      double s = 0.0;
-      for (int r = lane; r < a; r += 64) s += qc[r] * qc[r];
-      s = wave_sum(s);
-      if (lane == 0) {
-        cur[c] = s;
-        if (c == 0) nrm[0] = s;
-      }
-    }
-    __syncthreads();
-    double cmax = 0.0;  // largest |cos| between a column and an earlier one
-    for (int j = 0; j + 1 < a; ++j) {
-      const double nj = nrm[j];
-      const double* qj = Q + (size_t)j * a;
-      for (int c0 = j + 1 + wv * kMgsCols; c0 < a; c0 += nw * kMgsCols) {
-        const int nc = min(kMgsCols, a - c0);  // uniform in the wavefront
-        double dp[kMgsCols];
-#pragma unroll
-        for (int u = 0; u < kMgsCols; ++u) dp[u] = 0.0;
-        for (int r = lane; r < a; r += 64) {
-          const double q = qj[r];
-#pragma unroll
-          for (int u = 0; u < kMgsCols; ++u)
-            if (u < nc) dp[u] += q * Q[(size_t)(c0 + u) * a + r];
-        }
-        double coef[kMgsCols], sq[kMgsCols];
-#pragma unroll
-        for (int u = 0; u < kMgsCols; ++u) {
-          dp[u] = u < nc ? wave_sum(dp[u]) : 0.0;
-          coef[u] = nj > 0.0 ? dp[u] / nj : 0.0;
-          sq[u] = 0.0;
-        }
-        for (int r = lane; r < a; r += 64) {
-          const double q = qj[r];
-#pragma unroll
-          for (int u = 0; u < kMgsCols; ++u) {
-            if (u < nc) {
-              double* pc = Q + (size_t)(c0 + u) * a + r;
-              const double y = *pc - coef[u] * q;
-              *pc = y;
-              sq[u] += y * y;
-            }
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kMgsCols; ++u) {
-          if (u < nc) {
-            const int c = c0 + u;
-            const double cc = cur[c];
-            if (pass == 0 && nj > 0.0 && cc > 0.0) cmax = fmax(cmax, fabs(dp[u]) * rsqrt(nj) * rsqrt(cc));
-            if (c == j + 1) {
-              const double t = wave_sum(sq[u]);
-              if (lane == 0) nrm[c] = t;
-            } else if (lane == 0) {
-              cur[c] = fmax(cc - dp[u] * coef[u], 0.0);
-            }
-          }
-        }
-      }
-      __syncthreads();
-    }
-    for (int idx = tid; idx < aa; idx += kTriThreads) {
-      const double n2 = nrm[idx / a];
-      if (n2 > 0.0) Q[idx] *= 1.0 / sqrt(n2);
-    }
-    // the same second-pass decision in every thread
-    cmax = wave_max(cmax);
-    if (lane == 0) red[wv] = cmax;
-    __syncthreads();
-    double cm = 0.0;
-#pragma unroll
-    for (int i = 0; i < nw; ++i) cm = fmax(cm, red[i]);
-    if (pass == 0 && cm <= 1e-3) break;
-    __syncthreads();
-  }
-  for (int idx = tid; idx < aa; idx += kTriThreads) Xo[idx] = Q[idx];
-}
-
-// Block Gram-Schmidt for kTriLdsMax < a <= kPanelMax (left-looking, two
-// projections per panel, BCGS2): the columns, in eigenvalue order, are taken
-// in panels of kPanel; each panel is projected twice against all finished
+// Block Gram-Schmidt for a > kTriLdsMax (left-looking, two projections per
+// panel, BCGS2): the columns, in eigenvalue order, are taken in panels of
+// panel_width(a) (kPanel, fewer where a x kPanel doubles exceed the LDS
+// budget); each panel is projected twice against all finished
 // columns by two GEMMs on the matrix cores (W = Q_done^T P, P -= Q_done W),
 // then orthonormalised within itself by two passes of modified Gram-Schmidt
 // in LDS (k_mgs_panel).  The triangular structure is that of Gram-Schmidt,
@@ -794,7 +692,8 @@ __global__ __launch_bounds__(kTriThreads) void k_mgs(int a, const double* __rest
 // O(a^3) projection work runs on many compute units instead of streaming
 // the whole matrix through one.
 constexpr int kPanel = 32;
-constexpr int kPanelMax = 512;  // a x kPanel doubles in LDS
+constexpr int kPanelLds = 19200;  // doubles of LDS for one panel (150 KB)
+inline int panel_width(int a) { return std::max(1, std::min(kPanel, kPanelLds / a)); }
 
 // out (column-major) = transpose of in ([row][column]), a x a
 __global__ __launch_bounds__(256) void k_transpose_sq(int a, const double* __restrict__ in,
@@ -1043,12 +942,12 @@ void sym_eig(hipStream_t s, const double* G, int a, double* V, double* w, double
   check("sym_eig invit");
   if (a <= kTriLdsMax) {
     hipLaunchKernelGGL(k_mgs_reg, dim3(1), dim3(kRegThreads), 0, s, a, X, Xo);
-  } else if (a <= kPanelMax) {
-    const int nt = (a + 31) / 32;
+  } else {
+    const int nt = (a + 31) / 32, pw = panel_width(a);
     hipLaunchKernelGGL(k_transpose_sq, dim3(nt, nt), dim3(256), 0, s, a, X, Xo);
-    double* W = S;  // a x kPanel projection coefficients (S is free after the tridiagonalisation)
-    for (int k0 = 0; k0 < a; k0 += kPanel) {
-      const int nb = std::min(kPanel, a - k0);
+    double* W = S;  // a x pw projection coefficients (S is free after the tridiagonalisation)
+    for (int k0 = 0; k0 < a; k0 += pw) {
+      const int nb = std::min(pw, a - k0);
       double* Pk = Xo + (size_t)k0 * a;
       for (int rep = 0; k0 > 0 && rep < 2; ++rep) {
         dgemm(s, true, false, k0, nb, a, 1.0, Xo, a, 0, Pk, a, 0, 0.0, W, k0, 0);
@@ -1056,8 +955,6 @@ void sym_eig(hipStream_t s, const double* G, int a, double* V, double* w, double
       }
       hipLaunchKernelGGL(k_mgs_panel, dim3(1), dim3(kTriThreads), sizeof(double) * (size_t)a * nb, s, a, nb, Pk);
     }
-  } else {
-    hipLaunchKernelGGL(k_mgs, dim3(1), dim3(kTriThreads), sizeof(double) * 2 * a, s, a, X, Xo, S);
   }
   check("sym_eig mgs");
   // one wavefront per column; 8 per workgroup when columns live in LDS

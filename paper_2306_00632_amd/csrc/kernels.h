@@ -39,7 +39,8 @@ void householder_qr(hipStream_t s, const QrJob* jobs, int njobs);
 // Symmetric eigendecomposition G = V diag(w) V^T of an a x a matrix
 // (a <= 2048): Householder tridiagonalisation, multisection for the
 // eigenvalues, inverse iteration, two Gram-Schmidt passes and the back
-// transformation, five launches on stream s.  V is column-major with the
+// transformation on stream s (five launches up to order 136; beyond, the
+// Gram-Schmidt step runs by column panels with matrix-core GEMMs).  V is column-major with the
 // eigenvectors in descending eigenvalue order, w descending.  `work` holds
 // sym_eig_work(a) doubles.  G is not modified.
 size_t sym_eig_work(int a);

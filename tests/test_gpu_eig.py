@@ -11,8 +11,9 @@ The spectra cover the shapes the Gram matrices of the solver take: flat
 (clustered), geometrically graded over 16 and 30 decades (below the rounding
 level of G), low rank with an exactly zero tail, exactly repeated
 eigenvalues, the zero matrix, and the orders 1, 2, 3, the largest order the
-in-LDS path takes (136) and both sides of it, and a = 300 (global-memory
-path)."""
+in-LDS path takes (136) and both sides of it, a = 300 (block Gram-Schmidt
+with 32-column panels) and a = 700 (27-column panels, the LDS budget's
+width)."""
 import numpy as np
 import pytest
 
@@ -59,7 +60,7 @@ def run_eig(ctx, G):
     return V.cpu().numpy().reshape(a, a, order="F"), w.cpu().numpy()
 
 
-@pytest.mark.parametrize("a", [1, 2, 3, 17, 64, 129, 135, 136, 137, 300])
+@pytest.mark.parametrize("a", [1, 2, 3, 17, 64, 129, 135, 136, 137, 300, 700])
 @pytest.mark.parametrize("kind", ["flat", "graded16", "graded30", "lowrank", "repeated", "zero"])
 def test_sym_eig_properties(ctx, a, kind):
     say(f"sym_eig a={a} {kind}")
