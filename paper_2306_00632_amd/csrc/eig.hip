@@ -137,14 +137,16 @@ __device__ inline double unit_rand(unsigned long long key) {
 // to alpha e_1 with H_j = I - tau_j v_j v_j^T (v_j stored in column j of R,
 // rows j+1..a-1) and updates the trailing block as
 // S <- S - v w^T - w v^T, w = p - (tau/2)(p.v) v, p = tau S v.  This
-// version (a > kTriLdsMax) keeps S in global memory; k_tridiag_reg below
-// holds it in registers.
+// version (a > kTriLdsMax) keeps S in global memory and runs the steps
+// j < jstop; k_tridiag_reg below holds the matrix in registers and takes
+// over the trailing block of order kTriLdsMax (its steps cost about the same
+// whatever the trailing order, so the hand-off saves a - 2 - jstop of them).
 __global__ __launch_bounds__(kTriThreads) void k_tridiag(const double* __restrict__ G, int a,
                                                          double* Sg, double* __restrict__ R,
                                                          double* __restrict__ tau_out,
                                                          double* __restrict__ d,
                                                          double* __restrict__ e,
-                                                         double* __restrict__ misc) {
+                                                         double* __restrict__ misc, int jstop) {
   extern __shared__ double sm[];
   constexpr int ng = 4;
   double* S = Sg;
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(const double* __restric
   for (int i = tid; i < aa; i += kTriThreads) S[i] = G[i] * sc;
   __syncthreads();
 
-  for (int j = 0; j + 2 < a; ++j) {
+  for (int j = 0; j + 2 < a && j < jstop; ++j) {
     const int m = a - 1 - j;  // trailing order, >= 2
     const int o = j + 1;      // first trailing index
     const double* xj = S + (size_t)j * a + o;
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(const double* __restric
     }
     __syncthreads();
   }
-  if (tid == 0) {
+  if (tid == 0 && jstop + 2 >= a) {
     if (a >= 2) {
       d[a - 2] = S[(size_t)(a - 2) * a + a - 2];
       e[a - 2] = S[(size_t)(a - 2) * a + a - 1];
@@ -284,7 +286,8 @@ __global__ __launch_bounds__(kRegThreads) void k_tridiag_reg(const double* __res
                                                              double* __restrict__ tau_out,
                                                              double* __restrict__ d,
                                                              double* __restrict__ e,
-                                                             double* __restrict__ misc) {
+                                                             double* __restrict__ misc, int ld,
+                                                             int noscale) {
   constexpr int nw = kRegThreads / 64;
   __shared__ double vbuf[2][kPadRows], pbuf[kPadRows], colbuf[kPadRows];
   __shared__ double dl[kTriLdsMax], el[kTriLdsMax], tl[kTriLdsMax];
@@ -301,22 +304,25 @@ __global__ __launch_bounds__(kRegThreads) void k_tridiag_reg(const double* __res
     pbuf[i] = 0.0;
     colbuf[i] = 0.0;
   }
+  // G and R have leading dimension ld; with noscale the matrix is the
+  // trailing block of one already scaled (misc[0] is left as it is)
   double mx = 0.0;
-  for (int i = t; i < a * a; i += kRegThreads) mx = fmax(mx, fabs(G[i]));
+  if (!noscale)
+    for (int i = t; i < a * a; i += kRegThreads) mx = fmax(mx, fabs(G[(size_t)(i / a) * ld + i % a]));
   mx = wave_max(mx);
   if (lane == 0) red[wv] = mx;
   __syncthreads();
   if (t == 0) {
     double m = 0.0;
     for (int i = 0; i < nw; ++i) m = fmax(m, red[i]);
-    sc_s = (m > 0.0 && m <= DBL_MAX) ? ldexp(1.0, -ilogb(m)) : 1.0;
-    misc[0] = sc_s;
+    sc_s = noscale ? 1.0 : (m > 0.0 && m <= DBL_MAX) ? ldexp(1.0, -ilogb(m)) : 1.0;
+    if (!noscale) misc[0] = sc_s;
   }
   __syncthreads();
   const double sc = sc_s;
   double x[kRegRows];
 #pragma unroll
-  for (int k = 0; k < kRegRows; ++k) x[k] = (act && r0 + k < a) ? G[(size_t)c * a + r0 + k] * sc : 0.0;
+  for (int k = 0; k < kRegRows; ++k) x[k] = (act && r0 + k < a) ? G[(size_t)c * ld + r0 + k] * sc : 0.0;
   const double* prow = pbuf + r0;
 
   // Reflector of column jj, run by the whole wavefront that owns it: the
@@ -353,7 +359,7 @@ __global__ __launch_bounds__(kRegThreads) void k_tridiag_reg(const double* __res
       const int r = lane + 64 * m;
       const double vr = (tau == 0.0 || r <= jj) ? 0.0 : (r == jj + 1 ? v0 : col[m]);
       if (r < kPadRows) vb[r] = vr;
-      if (r > jj && r < a) R[(size_t)jj * a + r] = vr;
+      if (r > jj && r < a) R[(size_t)jj * ld + r] = vr;
     }
     if (lane == 0) {
       tau_s[jj & 1] = tau;
@@ -924,10 +930,17 @@ void sym_eig(hipStream_t s, const double* G, int a, double* V, double* w, double
   double* X = LU + 5 * aa;
   double* Xo = X + aa;
   if (a <= kTriLdsMax) {
-    hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(kRegThreads), 0, s, G, a, R, tau, d, e, misc);
+    hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(kRegThreads), 0, s, G, a, R, tau, d, e, misc, a, 0);
   } else {
+    // global-memory steps until the trailing order is kTriLdsMax, then the
+    // register kernel on that block of S (already scaled)
+    const int o0 = a - kTriLdsMax;
     hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kTriThreads), sizeof(double) * 6 * a, s, G, a, S, R, tau, d,
-                       e, misc);
+                       e, misc, o0);
+    check("sym_eig tridiag (global steps)");
+    const size_t off = (size_t)o0 * a + o0;
+    hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(kRegThreads), 0, s, S + off, kTriLdsMax, R + off, tau + o0,
+                       d + o0, e + o0, misc, a, 1);
   }
   check("sym_eig tridiag");
   hipLaunchKernelGGL(k_bisect, dim3((a + kBisWaves - 1) / kBisWaves), dim3(64 * kBisWaves),
