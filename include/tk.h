@@ -341,6 +341,16 @@ typedef struct {
                           eigendecomposition (tk_truncate_refinements); above
                           it the Gram eigenvectors alone decide the ranks, which
                           may then exceed the SVD-based ones (1e-8) */
+  int32_t reuse_bases; /* 1 (default): in every truncation of the solver, the
+                          mode-2 and mode-3 bases are the eigenvectors of the
+                          untruncated core's Gram matrices, computed on side
+                          streams while mode 1 runs, also after mode 1 was
+                          truncated; the discarded energies are measured on the
+                          sequentially truncated core, so ||y - T(y)|| <= eps ||y||
+                          holds exactly and the ranks are at least those of the
+                          exact ST-HOSVD (equal unless a cut is borderline).
+                          0: exact ST-HOSVD of Algorithm 1 (a fresh Gram matrix
+                          per truncated mode), as tucker_truncate does */
 } tk_tpcg_params;
 
 enum { TK_ARITH_MIXED = 2 };

@@ -611,7 +611,14 @@ static int refine_tail(tk_ctx* ctx, int a, int bc, int k1, const int* sel, doubl
   return k_add;
 }
 
-static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double* disc_rel, bool refine = true) {
+// With spec_any, modes 2 and 3 take the eigenvectors of the untruncated
+// core's Gram matrices (computed on the side streams while mode 1 runs) even
+// after an earlier mode was truncated; the energies are still measured on the
+// sequentially truncated core, so ||y - T(y)|| <= eps ||y|| holds exactly,
+// and the ranks can only exceed those of the exact ST-HOSVD (Ky Fan) in
+// borderline cases.  Without it such modes take a fresh Gram matrix.
+static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double* disc_rel, bool refine = true,
+                                  bool spec_any = false) {
   int dims[3] = {P.q[0], P.q[1], P.q[2]};
   BufP cur = P.Z;
   BufP S[3];
@@ -627,7 +634,8 @@ static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double*
     BufP V, Pm, part;
     if (k == 0) spec_launch(ctx, P);
     // the speculative eigenvectors hold when every earlier mode kept all its directions
-    const bool use_spec = k > 0 && P.Vs[k - 1] && s_k[0] == P.q[0] && (k == 1 || s_k[1] == P.q[1]);
+    const bool use_spec =
+        k > 0 && P.Vs[k - 1] && (spec_any || (s_k[0] == P.q[0] && (k == 1 || s_k[1] == P.q[1])));
     if (k == 0 && P.V0) {
       V = P.V0;
       Pm = P.Pm0;
@@ -740,9 +748,10 @@ static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double*
   return t;
 }
 
-static tk_tucker* truncate(tk_ctx* ctx, const tk_tucker* y, double eps, double* disc, bool refine = true) {
+static tk_tucker* truncate(tk_ctx* ctx, const tk_tucker* y, double eps, double* disc, bool refine = true,
+                           bool spec_any = false) {
   TruncPrep P = truncate_prepare(ctx, y);
-  return truncate_finish(ctx, P, eps, disc, refine);
+  return truncate_finish(ctx, P, eps, disc, refine, spec_any);
 }
 
 static double core_norm(tk_ctx* ctx, const tk_tucker* t) {
@@ -911,7 +920,7 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
   Owned r(scaled_copy(ctx, f.t, 1.0));  // r_0 = f (x_0 = 0)
   double nr = 1.0;
   if (r.t->blocks.size() != 1) {
-    r = Owned(truncate(ctx, r.t, 0.0, nullptr, 0.0 < prm.refine_below));
+    r = Owned(truncate(ctx, r.t, 0.0, nullptr, 0.0 < prm.refine_below, prm.reuse_bases != 0));
     nr = core_norm(ctx, r.t);
   }
   double eta = beta * tol / nr;
@@ -921,11 +930,11 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
     return on;
   };
   Owned pz(apply_prec(ctx, P, r.t, f32()));
-  Owned z(truncate(ctx, pz.t, eta, nullptr, eta < prm.refine_below));
+  Owned z(truncate(ctx, pz.t, eta, nullptr, eta < prm.refine_below, prm.reuse_bases != 0));
   pz = Owned();
   Owned p(scaled_copy(ctx, z.t, 1.0));
   Owned ap(apply_op(ctx, op, p.t, f32()));
-  Owned q(truncate(ctx, ap.t, eta, nullptr, eta < prm.refine_below));
+  Owned q(truncate(ctx, ap.t, eta, nullptr, eta < prm.refine_below, prm.reuse_bases != 0));
   ap = Owned();
   inf.trel_calls = 2;
   double xi = dot(ctx, p.t, q.t);
@@ -944,7 +953,7 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
     double eps_new = eps;
     Owned x1;
     while (true) {
-      x1 = Owned(truncate_finish(ctx, prep, eps_new, nullptr, eps_new < prm.refine_below));
+      x1 = Owned(truncate_finish(ctx, prep, eps_new, nullptr, eps_new < prm.refine_below, prm.reuse_bases != 0));
       ++inf.trel_calls;
       if (den == 0.0) break;
       const double v = (om * dot(ctx, p.t, x1.t) - base) / den;
@@ -959,7 +968,7 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
     Owned ax(apply_op(ctx, op, x.t));
     Owned res(lin_comb(ctx, 1.0, f.t, -1.0, ax.t));
     ax = Owned();
-    r = Owned(truncate(ctx, res.t, eta, nullptr, eta < prm.refine_below));
+    r = Owned(truncate(ctx, res.t, eta, nullptr, eta < prm.refine_below, prm.reuse_bases != 0));
     res = Owned();
     ++inf.trel_calls;
     nr = core_norm(ctx, r.t);
@@ -971,14 +980,14 @@ static tk_status tpcg(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_t
     if (nr <= tol) break;
     eta = beta * tol / nr;
     pz = Owned(apply_prec(ctx, P, r.t, f32()));
-    z = Owned(truncate(ctx, pz.t, eta, nullptr, eta < prm.refine_below));
+    z = Owned(truncate(ctx, pz.t, eta, nullptr, eta < prm.refine_below, prm.reuse_bases != 0));
     pz = Owned();
     const double bk = -dot(ctx, z.t, q.t) / xi;
     Owned zp(lin_comb(ctx, 1.0, z.t, bk, p.t));
-    p = Owned(truncate(ctx, zp.t, eta, nullptr, eta < prm.refine_below));
+    p = Owned(truncate(ctx, zp.t, eta, nullptr, eta < prm.refine_below, prm.reuse_bases != 0));
     zp = Owned();
     ap = Owned(apply_op(ctx, op, p.t, f32()));
-    q = Owned(truncate(ctx, ap.t, eta, nullptr, eta < prm.refine_below));
+    q = Owned(truncate(ctx, ap.t, eta, nullptr, eta < prm.refine_below, prm.reuse_bases != 0));
     ap = Owned();
     xi = dot(ctx, p.t, q.t);
     inf.trel_calls += 3;
@@ -1034,7 +1043,7 @@ static tk_status tpcg_block(tk_ctx* ctx, const tk_op* const A[9], const tk_prec*
     for (int a = 0; a < 3; ++a) out[a] = v[a].t;
   };
   auto trunc = [&](Owned* y, double eps, Owned* out) {
-    for (int a = 0; a < 3; ++a) out[a] = Owned(truncate(ctx, y[a].t, eps, nullptr, eps < prm.refine_below));
+    for (int a = 0; a < 3; ++a) out[a] = Owned(truncate(ctx, y[a].t, eps, nullptr, eps < prm.refine_below, prm.reuse_bases != 0));
     inf.trel_calls += 1;
   };
   // ||r|| of a truncated block vector (orthonormal factors per component)
@@ -1108,7 +1117,7 @@ static tk_status tpcg_block(tk_ctx* ctx, const tk_op* const A[9], const tk_prec*
     double eps_new = eps;
     Owned x1[3];
     while (true) {
-      for (int a = 0; a < 3; ++a) x1[a] = Owned(truncate_finish(ctx, prep[a], eps_new, nullptr, eps_new < prm.refine_below));
+      for (int a = 0; a < 3; ++a) x1[a] = Owned(truncate_finish(ctx, prep[a], eps_new, nullptr, eps_new < prm.refine_below, prm.reuse_bases != 0));
       ++inf.trel_calls;
       if (den == 0.0) break;
       const double v = (om * bdot(p, x1) - base) / den;
@@ -1963,6 +1972,7 @@ void tk_tpcg_defaults(tk_tpcg_params* p) {
   p->verbose = 0;
   p->arith = TK_ARITH_F64;
   p->refine_below = 1e-8;
+  p->reuse_bases = 1;
 }
 
 tk_status tpcg_solve(tk_ctx* ctx, const tk_op* op, const tk_prec* P, const tk_tucker* f,

@@ -37,7 +37,7 @@ class TpcgParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("beta", C.c_double), ("eps0", C.c_double),
                 ("alpha", C.c_double), ("eps_min", C.c_double), ("delta", C.c_double),
                 ("maxit", C.c_int32), ("verbose", C.c_int32), ("arith", C.c_int32),
-                ("refine_below", C.c_double)]
+                ("refine_below", C.c_double), ("reuse_bases", C.c_int32)]
 
 
 class TpcgInfo(C.Structure):

@@ -57,6 +57,27 @@ def test_tpcg_deformed_against_full_reference(setup, tol, eps_min, bound, arith)
         assert info["f32_applications"] == 0
 
 
+def test_tpcg_reuse_bases_both_ways(setup):
+    """reuse_bases = 1 (the solver default: mode-2 and mode-3 bases from the
+    untruncated core's Gram matrices, energies measured on the truncated
+    core) and 0 (the exact ST-HOSVD of Algorithm 1 in every truncation):
+    both meet the bound against the full-tensor reference at tol 1e-7, with
+    iteration counts within 1 of each other and solution ranks at least the
+    exact variant's minus 2 (the ranks of one truncation can only grow, but
+    the iterates then differ)."""
+    from paper_2306_00632_amd import tk
+    ctx, w, xr, (op, P, f) = setup
+    out = {}
+    for reuse in (0, 1):
+        x, info = tk.tpcg_solve(ctx, op, P, f, tol=1e-7, eps_min=1e-9, maxit=300, reuse_bases=reuse)
+        err = rel(to_oracle_plain(x).full(), xr)
+        say(f"   reuse_bases={reuse}: iters={info['iters']} rank={info['rank']} rel_err={err:.2e}")
+        assert info["converged"] and err < 1e-6
+        out[reuse] = info
+    assert abs(out[1]["iters"] - out[0]["iters"]) <= 1
+    assert min(out[1]["rank"][k] - out[0]["rank"][k] for k in range(3)) >= -2
+
+
 def test_tpcg_mid_size_matches_oracle_iterations():
     """n_el = 64 (65 dofs): GPU TPCG against the oracle's TPCG (iteration
     count within max(2, 10%)) and against the full-tensor reference."""
