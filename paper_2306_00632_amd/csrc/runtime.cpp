@@ -421,9 +421,10 @@ struct TruncPrep {
   // and energies are kept for the retries of Algorithm 2 on the same tensor
   BufP V0, Pm0, part0;
   // speculative eigenvectors of the Gram matrices of modes 2 and 3 of Z
-  // (computed on the side streams; valid for the sequential ST-HOSVD when the
+  // (computed on the side streams; exact for the sequential ST-HOSVD when the
   // earlier modes keep every direction, since an orthogonal rotation in one
-  // mode leaves the Gram matrices of the others unchanged)
+  // mode leaves the Gram matrices of the others unchanged, and used as the
+  // bases of those modes after a truncation too when the caller asks for it)
   bool spec = false;
   BufP Vs[2];
   std::vector<BufP> spec_keep;
@@ -633,7 +634,8 @@ static tk_tucker* truncate_finish(tk_ctx* ctx, TruncPrep& P, double eps, double*
     const int nseg = gpu::column_energy_parts(bc);
     BufP V, Pm, part;
     if (k == 0) spec_launch(ctx, P);
-    // the speculative eigenvectors hold when every earlier mode kept all its directions
+    // the speculative eigenvectors are the exact ST-HOSVD bases when every earlier
+    // mode kept all its directions; with spec_any they serve in any case
     const bool use_spec =
         k > 0 && P.Vs[k - 1] && (spec_any || (s_k[0] == P.q[0] && (k == 1 || s_k[1] == P.q[1])));
     if (k == 0 && P.V0) {
