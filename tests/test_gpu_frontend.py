@@ -109,6 +109,11 @@ def test_tpcg_annulus_against_direct_and_manufactured(ctx):
         X = to_oracle_plain(x).full()
         err = rel(X, _oracle_solution(n_el, p, t_op, t_rhs, eps))
         errs.append(_error_to_manufactured(X, n_el, p, u))
+        # the library's evaluation of the spline solution (tk_basis_values_1d)
+        # against the oracle's basis values on the same points
+        e = np.linspace(0.05, 0.95, 9)
+        Bs = bspline.dirichlet_basis_at(n_el, p, e)
+        assert rel(geometry.evaluate(x, n_el, p, e, e, e), np.einsum("abc,ia,jb,kc->ijk", X, Bs, Bs, Bs)) <= 1e-12
         say(f"   iters={info['iters']} rank={info['rank']} rel_vs_direct={err:.2e} err_u={errs[-1]:.3e}")
         assert info["converged"]
         assert err <= 1e-6
