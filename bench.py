@@ -494,6 +494,7 @@ def main():
     prec = problem.preconditioner(ctx, w, exact=(args.fd == "exact"))
     f = problem.rhs(ctx, w)
     params = dict(tol=w.tol, eps_min=w.eps_min, arith=args.arith)
+    prm_used = tk.tpcg_params(**params)  # the solver defaults plus these, for the bench line
     for _ in range(args.warmup):
         x, info = tk.tpcg_solve(ctx, op, prec, f, **params)
         del x
@@ -571,7 +572,8 @@ def main():
                    "kronecker_terms": len(w.nnz), "rhs_rank": int(np.asarray(problem.rhs_arrays(w)[0]).shape[0]),
                    "tol": w.tol, "iters": last_info["iters"], "relres": last_info["relres"],
                    "solution_rank": list(last_info["rank"]), "trel_calls": last_info["trel_calls"],
-                   "tail_refinements_per_solve": refinements},
+                   "tail_refinements_per_solve": refinements, "eps_min": w.eps_min,
+                   "refine_below": prm_used.refine_below, "reuse_bases": prm_used.reuse_bases},
         "latency_ms": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99)),
                        "min": min(ms), "max": max(ms)},
         "mode_product_GB_s": mode_gbs,
