@@ -14,7 +14,7 @@ truncations act blockwise with the machinery of Secs. 2.3 and 4:
 * the preconditioner is block diagonal, one low-rank FD (Algorithm 4) per
   component, with the component's direction coefficients.
 
-Readings (listed in the design doc): the paper builds the blocks from a mapped
+Readings of the paper taken here: the paper builds the blocks from a mapped
 column by a Chebyshev/Tucker fit of the geometry coefficients (App. A);
 here they come from the seeded recipe of ``workloads.elasticity`` (a
 weighted cube, Dirichlet on all faces).

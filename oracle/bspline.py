@@ -4,7 +4,7 @@ Follows Sec. 2.1 (open uniform knot vectors, Cox-de Boor recursion with the
 convention 0/0 = 0) and the univariate integrals of Appendix A
 (int delta(b_i) delta(b_j) w, with delta either the identity or d/dx).
 
-Readings of the paper (listed in the design doc):
+Readings of the paper taken here:
 * the degree-0 rule of Sec. 2.1 is half-open, which would make the last
   basis function vanish at x = 1; the last non-empty knot span is closed at
   its right end so that the basis is a partition of unity on [0, 1];

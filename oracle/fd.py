@@ -16,7 +16,7 @@ Appendix B (Dirichlet at both ends) is built densely, as written:
   (breakpoints for odd p, span midpoints for even p), collocation matrix
   C_ij = v_i(x_j), U_dft = sqrt(2) sin(j pi x_i), Lambda1 = (j pi)^2,
   V_h2 = M-orthogonal complement of V_h1 with its exact small eigenproblem.
-Readings (listed in DESIGN.md):
+Readings of the paper taken here:
 * "C^{-1} U_dft" is the interpolation in V_h1 of the sampled sines (the
   coefficients a with sum_i a_i v_i(x_j) = U_dft[j, :]);
 * "normalized in the L^2 norm": every approximate eigenvector function (a

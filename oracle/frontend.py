@@ -5,7 +5,7 @@ a tensor grid and a Tucker truncation of the coefficient tensor, and the
 Tucker matrix and vector they induce (eq. matrix_CP and the rhs factors
 F~_t).
 
-Readings (listed in DESIGN.md):
+Readings of the paper taken here:
 * the paper calls chebfun3f, which builds the Tucker form by cross
   approximation without the full evaluation tensor; here the full tensor of
   values on a Chebyshev-Lobatto grid of t points per direction is formed

@@ -4,7 +4,7 @@ All vectors are Tucker vectors; products use eq. (tt_product), scalar
 products Sec. 2.3, truncations Algorithms 1 and 2, the preconditioner
 Algorithm 4.
 
-Readings (listed in DESIGN.md):
+Readings of the paper taken here:
 * the rhs is normalised to ||f|| = 1 internally and the solution scaled back,
   so the absolute test ||r_k|| > tol of Algorithm 5 and the "relative
   tolerance" of Sec. 5 agree; eps_min = tol ||f~|| / 10 (Sec. 5) is taken
