@@ -207,3 +207,18 @@ def test_basis_values_1d_matches_oracle(bc, p):
         assert np.abs(B - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), der
     with pytest.raises(tk.TkError):
         tk.basis_values_1d(n_el, p, [1.5], 0, bc)
+
+
+def test_tpcg_defaults():
+    """tk_tpcg_defaults (host): Sec. 5's parameters (tol 1e-6, beta 0.1,
+    eps0 0.1, alpha 0.5, delta 1e-3, eps_min from the rhs), FP64 arithmetic,
+    the tail refinement below 1e-8 and the reuse of the speculative bases;
+    tk_truncate_refinements rejects a null context."""
+    from paper_2306_00632_amd import tk
+    prm = tk.tpcg_params()
+    assert (prm.tol, prm.beta, prm.eps0, prm.alpha, prm.delta) == (1e-6, 0.1, 0.1, 0.5, 1e-3)
+    assert prm.eps_min == 0.0 and prm.maxit == 1000 and prm.arith == tk.ARITH["f64"]
+    assert prm.refine_below == 1e-8 and prm.reuse_bases == 1
+    assert tk.tpcg_params(reuse_bases=0, arith="mixed").reuse_bases == 0
+    c = tk.C.c_int64()
+    assert tk.lib().tk_truncate_refinements(None, tk.C.byref(c)) == tk.TK_EINVAL
