@@ -222,3 +222,27 @@ def test_tpcg_defaults():
     assert tk.tpcg_params(reuse_bases=0, arith="mixed").reuse_bases == 0
     c = tk.C.c_int64()
     assert tk.lib().tk_truncate_refinements(None, tk.C.byref(c)) == tk.TK_EINVAL
+
+
+def test_new_setup_entries_reject_bad_arguments():
+    """The documented EINVAL cases of tk_assemble_1d_cheb,
+    tk_load_vector_1d_cheb and tk_basis_values_1d: no coefficients or more
+    than 4096, a flag other than 0 or 1, a derivative order above p, a point
+    outside [0, 1]."""
+    from paper_2306_00632_amd import tk
+    L = tk.lib()
+    c = np.ones(4)
+    band = np.zeros((5, 12))
+    F = np.zeros(12)
+    cp, bp, Fp = (x.ctypes.data_as(tk.dp) for x in (c, band, F))
+    assert L.tk_assemble_1d_cheb(10, 2, 0, 0, cp, 0, 0, bp) == tk.TK_EINVAL
+    assert L.tk_assemble_1d_cheb(10, 2, 0, 4097, cp, 0, 0, bp) == tk.TK_EINVAL
+    assert L.tk_assemble_1d_cheb(10, 2, 0, 4, cp, 2, 0, bp) == tk.TK_EINVAL
+    assert L.tk_assemble_1d_cheb(10, 2, 0, 4, cp, 0, 0, bp) == tk.TK_OK
+    assert L.tk_load_vector_1d_cheb(10, 2, 0, cp, 0, 0, Fp) == tk.TK_EINVAL
+    assert L.tk_load_vector_1d_cheb(10, 2, 4, cp, 0, 3, Fp) == tk.TK_EINVAL
+    with pytest.raises(tk.TkError):
+        tk.basis_values_1d(10, 2, [0.5], der=3)
+    with pytest.raises(tk.TkError):
+        tk.basis_values_1d(10, 2, [-0.1])
+    assert tk.basis_values_1d(10, 2, [], der=1).shape == (0, 10)
